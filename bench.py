@@ -1,0 +1,278 @@
+"""Benchmark of the wavelet stage on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1]
+
+One step = the whole hot path over one batch: every field of the workload is
+compressed (3D forward transform, decimation, mask, compaction, offsets,
+header) and then decompressed (unpack, inverse transform, store), all
+device-resident.  The default workload is one GPU's share of the paper's
+large in-situ runs: five 1024^3 float64 fields (density- and pressure-like
+bubble clouds, three divergence-free velocity components), W3_ai, 32^3
+blocks, eps = 1e-4 of each field's range.
+
+Prints one JSON line: value = raw field bytes per step / step time (GB/s,
+1e9 B), forward and inverse rates, per-field PSNR (Eq. 1), max error and
+compression ratio, the roofline of the dominant kernel (algorithmic bytes =
+raw field + stream per launch, timed with HIP events on the launch stream)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sources_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1903_07761_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + fh.read())
+    return h.hexdigest()
+
+
+def workload(name: str, device):
+    """[(label, field tensor, scheme, block, eps)] and a description."""
+    import torch
+
+    from paper_1903_07761_amd import fields as G
+
+    out = []
+    if name == "c3":
+        n, dt = 1024, torch.float64
+        log("generating 5 x 1024^3 float64 fields")
+        rho = G.bubble_cloud(n, 1905, v_in=0.016, dtype=dt, device=device)
+        out.append(("rho", rho))
+        p = G.bubble_cloud(n, 1905, v_in=0.1, noise_seed=1906, dtype=dt, device=device)
+        out.append(("p", p))
+        for lab, comp in zip(("u", "v", "w"), G.div_free_velocity(n, 1907, dtype=dt, device=device)):
+            out.append((lab, comp))
+        desc = ("5 x 1024^3 float64 fields (rho, p: 200-bubble clouds with 1% noise; u, v, w: divergence-free "
+                "sinusoid sums), W3_ai, block 32^3, eps 1e-4 of each field's range")
+        scheme, block, frac = "W3_ai", 32, 1e-4
+    elif name == "c2":
+        log("generating 512^3 float32 bubble cloud")
+        out.append(("p", G.bubble_cloud(512, 1904, dtype=torch.float32, device=device)))
+        desc = "512^3 float32 bubble cloud (pressure-like), W4_li, block 32^3, eps 1e-3 of range"
+        scheme, block, frac = "W4_li", 32, 1e-3
+    else:
+        out.append(("f", G.gaussian_bumps(128, 1903, dtype=torch.float32, device=device)))
+        desc = "128^3 float32 Gaussian bumps, W4, block 32^3, eps 1e-3 of range"
+        scheme, block, frac = "W4", 32, 1e-3
+    items = [(lab, t, scheme, block, frac * G.value_range(t)) for lab, t in out]
+    return items, desc
+
+
+def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2 * nbytes / t / 1e9
+
+
+def cpu_baseline(items, blocks_per_field: int):
+    """The oracle (single thread) on blocks [0, k) of every field."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    t_fwd = t_inv = 0.0
+    raw = 0
+    for lab, t, scheme, N, eps in items:
+        nz, ny, nx = t.shape
+        per_layer = (nx // N) * (ny // N)
+        layers = -(-blocks_per_field // per_layer)
+        sub = t[:layers * N].cpu().numpy()
+        k = min(blocks_per_field, per_layer * layers)
+        t0 = time.perf_counter()
+        recs, sizes = oracle.compress_blocks(sub, N, scheme, eps, 0, k)
+        t1 = time.perf_counter()
+        back = np.zeros_like(sub)
+        oracle.decompress_blocks(recs, sizes, sub.shape, N, scheme, 0, k, back)
+        t2 = time.perf_counter()
+        t_fwd += t1 - t0
+        t_inv += t2 - t1
+        raw += k * N ** 3 * sub.dtype.itemsize
+        log(f"cpu oracle {lab}: {k} blocks fwd {t1 - t0:.2f}s inv {t2 - t1:.2f}s")
+    return raw, t_fwd, t_inv
+
+
+def traffic_record(kernel: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("sources_sha256") != sources_sha():
+        return None
+    return rec.get("kernels", {}).get(kernel)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1"])
+    ap.add_argument("--cpu-blocks", type=int, default=400, help="oracle sample: blocks per field")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU exchange is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1903_07761_amd import metrics
+    from paper_1903_07761_amd.codec import Codec
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda", 0)
+    codec = Codec(0)
+    items, desc = workload(args.workload, dev)
+    stream = torch.cuda.current_stream(dev)
+
+    # buffers: one stream per field, one reconstruction buffer per field
+    streams, recons, exp_params = [], [], []
+    for lab, t, scheme, N, eps in items:
+        cap = codec.bound(t.shape, t.dtype, N)
+        streams.append(torch.empty(cap, dtype=torch.uint8, device=dev))
+        recons.append(torch.empty_like(t))
+        exp_params.append(codec.params(t, N, scheme, eps))
+    nbytes_dev = torch.zeros(len(items), dtype=torch.int64, device=dev)
+    codec.ctx.reserve(max(t.numel() // N ** 3 for _, t, _, N, _ in items))
+
+    def step(events=None):
+        for i, (lab, t, scheme, N, eps) in enumerate(items):
+            if events is not None:
+                events[i][0].record(stream)
+            codec.compress(t, N, scheme, eps, out=streams[i], sync=False, out_bytes=nbytes_dev[i:i + 1])
+            if events is not None:
+                events[i][1].record(stream)
+            codec.decompress(streams[i], streams[i].numel(), out=recons[i], expected=exp_params[i])
+            if events is not None:
+                events[i][2].record(stream)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = codec.status()
+    if st != 0:
+        raise SystemExit(f"device status {st} after warmup")
+
+    log(f"timing {args.steps} steps")
+    ev = [[[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in items] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = codec.status()
+    if st != 0:
+        raise SystemExit(f"device status {st} after timing")
+
+    sizes = [int(x) for x in nbytes_dev.cpu().tolist()]
+    raw = [t.numel() * t.element_size() for _, t, _, _, _ in items]
+    fwd_ms = [sum(ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)) / args.steps
+              for i in range(len(items))]
+    inv_ms = [sum(ev[s][i][1].elapsed_time(ev[s][i][2]) for s in range(args.steps)) / args.steps
+              for i in range(len(items))]
+    ms_per_step = wall * 1e3 / args.steps
+    raw_total = sum(raw)
+    value = raw_total / (ms_per_step / 1e3) / 1e9
+    fwd_gbps = raw_total / (sum(fwd_ms) / 1e3) / 1e9
+    inv_gbps = raw_total / (sum(inv_ms) / 1e3) / 1e9
+
+    # algorithmic bytes per launch = raw field + stream, both directions
+    algo = [r + s for r, s in zip(raw, sizes)]
+    fwd_rate = sum(algo) / (sum(fwd_ms) / 1e3) / 1e9
+    inv_rate = sum(algo) / (sum(inv_ms) / 1e3) / 1e9
+    dominant = "fwd" if sum(fwd_ms) >= sum(inv_ms) else "inv"
+    achieved = fwd_rate if dominant == "fwd" else inv_rate
+    kname = "fwd_kernel" if dominant == "fwd" else "inv_kernel"
+    tr = traffic_record(kname)
+
+    log("quality")
+    psnr, maxerr, cr = [], [], []
+    for i, (lab, t, scheme, N, eps) in enumerate(items):
+        p, m = metrics.error_stats(t, recons[i])
+        psnr.append(round(p, 2))
+        maxerr.append(float(f"{m:.4g}"))
+        cr.append(round(raw[i] / sizes[i], 3))
+
+    log("copy bandwidth")
+    copy_gbps = copy_bandwidth(torch)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one thread)")
+        craw, cf, ci = cpu_baseline(items, args.cpu_blocks)
+        cpu = {"value": round(craw / (cf + ci) / 1e9, 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"blocks [0, {args.cpu_blocks}) of each field ({len(items) * args.cpu_blocks} blocks), "
+                         f"forward + inverse, single-threaded",
+               "fwd_GBps": round(craw / cf / 1e9, 5), "inv_GBps": round(craw / ci / 1e9, 5)}
+
+    dtype = {torch.float32: "f32", torch.float64: "f64"}[items[0][1].dtype]
+    line = {
+        "metric": "GB/s raw field (FWT+threshold+pack, and inverse)",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": desc, "fields": len(items), "grid": list(items[0][1].shape), "block": items[0][3],
+                   "scheme": items[0][2], "raw_bytes_per_step": raw_total},
+        "fwd_GBps": round(fwd_gbps, 2),
+        "inv_GBps": round(inv_gbps, 2),
+        "psnr_db": psnr,
+        "max_err": maxerr,
+        "cr_stage1": cr,
+        "copy_GBps": round(copy_gbps, 1),
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "frac_of_copy": round(achieved / copy_gbps, 4),
+                     "traffic": tr, "fwd_GBps_algo": round(fwd_rate, 1), "inv_GBps_algo": round(inv_rate, 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

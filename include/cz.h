@@ -1,0 +1,140 @@
+/*
+ * cz.h -- C ABI of the CubismZ wavelet stage on MI355X (gfx950).
+ *
+ * The operation (Hadjidoukas & Wermelinger, arXiv 1903.07761):
+ *   Sec. 2.1-2.2  the field is one scalar quantity on a grid of equal cubic
+ *                 blocks of power-of-two edge N; blocks are the unit of work.
+ *   Sec. 2.3      "Wavelet-based compression": per block, a 3D forward wavelet
+ *                 transform with filters on the interval (no data from
+ *                 neighbouring blocks), then decimation of the detail
+ *                 coefficients below eps, output = bit-set mask + stream of
+ *                 significant coefficients.  "Wavelet types": W4 (fourth-order
+ *                 interpolating), W4_li (its lifted form), W3_ai (third-order
+ *                 average-interpolating).
+ *   Sec. 2.3      "Data decompression": block-level inverse transform.
+ *   Sec. 2.2      the exclusive prefix scan of compressed sizes that places
+ *                 each piece in the output.
+ *
+ * Stream format (little-endian), produced by cz_compress, consumed by
+ * cz_decompress:
+ *   [0, 64)      header: char magic[4] = "CZB1"; u32 version = 1, scheme,
+ *                elem_bytes, N, levels = log2(N) - 2, nx, ny, nz, reserved = 0;
+ *                f64 epsilon; u64 nblocks; u64 payload_bytes
+ *   [64, ...)    (nblocks + 1) u64 record offsets relative to the payload,
+ *                off[0] = 0, off[b+1] = off[b] + record_bytes(b)
+ *   pad          zeros up to payload start P = roundup16(64 + 8 (nblocks + 1))
+ *   P + off[b]   record of block b = bx + nbx (by + nby bz):
+ *                  u32 nnz (kept coefficients, the 64 coarse ones included),
+ *                  u32 flags = 0,
+ *                  N^3 / 8 mask bytes: bit q (q = x + N (y + N z), Mallat
+ *                  layout) is bit (q & 7) of byte (q >> 3),
+ *                  nnz values of the field type in ascending q,
+ *                  zero padding to a multiple of 16 bytes.
+ *   total bytes  P + off[nblocks]
+ *
+ * The transform (all arithmetic in the field precision, no fused
+ * multiply-add, weighted sums left to right in ascending source index):
+ *   one level of a line of n samples -> [n/2 coarse | n/2 details]:
+ *     W4    detail m = odd m - cubic through the four nearest existing evens
+ *           at m + 1/2; coarse = evens.
+ *     W4_li W4, then coarse k += sum over details m = k-2..k+1 (those that
+ *           exist) of (-1, 9, 9, -1)/32 d_m.
+ *     W3_ai coarse k = (v[2k] + v[2k+1]) / 2; detail k = v[2k] - the average
+ *           over [k, k+1/2] of the quadratic matching the three nearest
+ *           existing coarse averages.
+ *   3D: for n = N, N/2, ..., 8: x-lines, then y-lines, then z-lines of
+ *   [0,n)^3; inverse for n = 8..N: z, y, x.  Decimation keeps q when q lies
+ *   in the 4^3 coarse corner or (double)|c_q| >= eps; dropped values decode
+ *   as +0.0.
+ *
+ * Conventions.  Every pointer named d_* is device memory of the context's
+ * device, owned by the caller; the library keeps none of them after a call
+ * returns, and never allocates on the compress/decompress paths once the
+ * context's workspace is large enough (cz_reserve).  Calls are ordered on the
+ * given HIP stream (hipStream_t passed as void*; NULL = the null stream).  A
+ * context's workspace is shared by its calls: calls on one context must not
+ * overlap in time (issue them on one stream, or synchronise between them).
+ * All functions return 0 (CZ_OK) or a negative CZ_ERR_* code; nothing throws.
+ */
+#ifndef CZ_H
+#define CZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { CZ_W4 = 0, CZ_W4_LI = 1, CZ_W3_AI = 2 };
+
+enum {
+    CZ_OK = 0,
+    CZ_ERR_ARG = -1,       /* null pointer, bad enum, eps < 0 or non-finite   */
+    CZ_ERR_SHAPE = -2,     /* N not in {8,16,32,64} or an edge not a multiple */
+    CZ_ERR_CAPACITY = -3,  /* output buffer too small (required size returned) */
+    CZ_ERR_NONFINITE = -4, /* non-finite input or coefficient; output undefined */
+    CZ_ERR_FORMAT = -5,    /* corrupt or inconsistent stream                   */
+    CZ_ERR_HIP = -6,       /* HIP runtime failure                              */
+    CZ_ERR_BUDGET = -7,    /* request larger than a server's memory budget     */
+    CZ_ERR_TIMEOUT = -8    /* a device-side wait exceeded its bound             */
+};
+
+typedef struct {
+    uint32_t nx, ny, nz;  /* grid edges, x fastest in memory (C order [z][y][x]) */
+    uint32_t block;       /* N in {8, 16, 32, 64}; every edge a multiple of N    */
+    uint32_t scheme;      /* CZ_W4 | CZ_W4_LI | CZ_W3_AI                          */
+    uint32_t elem_bytes;  /* 4 (float) or 8 (double)                              */
+    double epsilon;       /* absolute decimation threshold, finite and >= 0      */
+} cz_params;
+
+typedef struct cz_ctx cz_ctx;
+
+/* Create a context on HIP device `device` (allocates a small workspace and a
+ * pinned status word).  Returns CZ_ERR_HIP if the device is unusable. */
+int cz_create(cz_ctx **out, int device);
+void cz_destroy(cz_ctx *ctx);
+
+/* Grow the context's workspace so that fields of up to max_blocks blocks need
+ * no allocation later.  Optional: compress/decompress grow it on demand. */
+int cz_reserve(cz_ctx *ctx, uint64_t max_blocks);
+
+/* Worst-case stream size (every coefficient kept) for params p, or 0 when p
+ * is invalid.  = P + nblocks * roundup16(8 + N^3/8 + N^3 elem_bytes). */
+size_t cz_compress_bound(const cz_params *p);
+
+/* Compress the device field d_field (nx*ny*nz elements, [z][y][x]) into the
+ * stream at d_out (capacity out_cap bytes, >= cz_compress_bound or
+ * CZ_ERR_CAPACITY with the bound written to *h_out_bytes when non-null).
+ * Synchronous when h_out_bytes != NULL: waits for the stream and returns the
+ * stream size and any device-detected error (CZ_ERR_NONFINITE,
+ * CZ_ERR_TIMEOUT), which is then cleared.  Otherwise fully asynchronous: the size is written to the
+ * device u64 *d_out_bytes (if non-null) and device errors are read with
+ * cz_get_status before the context's next call. */
+int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_out, size_t out_cap,
+                uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream);
+
+/* Rebuild the field from the stream d_in (in_bytes long) into d_field
+ * (field_cap bytes).  With expected == NULL the 64-byte header is read back
+ * (synchronous), and the call waits for completion and returns (and clears)
+ * any device-detected error (CZ_ERR_FORMAT for an inconsistent record; such
+ * blocks are left unwritten).  With
+ * expected != NULL (it must match the header) the call is asynchronous and
+ * device errors are read with cz_get_status. */
+int cz_decompress(cz_ctx *ctx, const cz_params *expected, const void *d_in, size_t in_bytes, void *d_field,
+                  size_t field_cap, void *stream);
+
+/* Wait for `stream`, then return and clear the error latched by the
+ * context's asynchronous calls (CZ_OK if none). */
+int cz_get_status(cz_ctx *ctx, void *stream);
+
+/* Parse a host copy of a stream header (n >= 64 bytes). */
+int cz_read_header(const void *h_hdr, size_t n, cz_params *out, uint64_t *nblocks, uint64_t *total_bytes);
+
+const char *cz_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CZ_H */

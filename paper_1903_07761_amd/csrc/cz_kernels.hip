@@ -1,0 +1,747 @@
+// HIP kernels of the CubismZ wavelet stage for MI355X (gfx950).
+//
+// Paper: arXiv 1903.07761.  Sec. 2.3 ("Wavelet-based compression", "Wavelet
+// types", "Data decompression") defines the per-block 3D transform, the
+// decimation at eps and the mask + coefficient stream; Sec. 2.2 places each
+// compressed piece with an exclusive prefix scan of the sizes.
+//
+// Design (one workgroup per N^3 block at a time, persistent over a block
+// ticket counter):
+//   * the workgroup has N*N threads; thread (x, y) owns the z-column of the
+//     block in VGPRs, so the global load and store of a block are coalesced
+//     rows (consecutive x in consecutive lanes);
+//   * the finest level runs its x- and y-lines through LDS one group of Z
+//     z-slabs at a time (Z = N keeps a 32^3 float block whole in LDS; double
+//     blocks, 256 KiB at N = 32, are staged by slab), each line transformed
+//     in registers by one thread, then the z-lines in registers;
+//   * the coarser levels (at most (N/2)^3) run entirely in LDS;
+//   * decimation: one wavefront ballot per 64 consecutive coefficients gives a
+//     mask word directly in the stream's bit order; word popcounts are scanned
+//     across the workgroup, and each kept value's rank is the word prefix plus
+//     mbcnt of its lanes below;
+//   * record offsets: a single-pass decoupled look-back over block tickets
+//     (each block publishes its record size as soon as its nnz is known, then
+//     accumulates predecessors until it meets an inclusive prefix);
+//   * the inverse mirrors the forward: mask words to LDS, ranks by prefix
+//     popcount, gather, coarse levels in LDS, z-lines in registers, y and x
+//     lines by slab group through LDS, coalesced store.
+// The path is a short stencil plus a scan: bound by HBM bandwidth, no MFMA.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cz_lines.h"
+#include "cz_kernels.h"
+
+namespace czk {
+
+static constexpr uint64_t FLAG_AGG = 1ull << 62;
+static constexpr uint64_t FLAG_INC = 2ull << 62;
+static constexpr uint64_t FLAG_VAL = (1ull << 62) - 1;
+static constexpr uint32_t LOOKBACK_SPIN_LIMIT = 1u << 24;
+
+__device__ __forceinline__ uint64_t atomic_load_u64(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_store_u64(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back (single thread): publish this block's record size,
+// return the sum of the sizes of all earlier blocks.  Every wait is bounded;
+// on exhaustion the status word gets STATUS_TIMEOUT and 0 is returned.
+__device__ uint64_t lookback(uint64_t *flags, uint64_t b, uint64_t size, uint32_t *status)
+{
+    if (b == 0) {
+        atomic_store_u64(&flags[0], FLAG_INC | size);
+        return 0;
+    }
+    atomic_store_u64(&flags[b], FLAG_AGG | size);
+    uint64_t excl = 0;
+    uint64_t j = b - 1;
+    uint32_t spins = 0;
+    while (true) {
+        uint64_t f = atomic_load_u64(&flags[j]);
+        uint64_t st = f & ~FLAG_VAL;
+        if (st == 0) {
+            if (++spins > LOOKBACK_SPIN_LIMIT) {
+                atomicOr(status, STATUS_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        excl += f & FLAG_VAL;
+        if (st == FLAG_INC)
+            break;
+        --j;
+    }
+    atomic_store_u64(&flags[b], FLAG_INC | (excl + size));
+    return excl;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Exclusive scan of one u32 per thread over a workgroup of NT threads.
+// s_w must hold NT/64 + 1 words; the total lands in s_w[NT/64].
+template <int NT>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_w)
+{
+    constexpr int NW = NT / 64;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / 64;
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t t = __shfl_up(inc, off, 64);
+        if (lane >= (uint32_t)off)
+            inc += t;
+    }
+    if constexpr (NW == 1) {
+        if (lane == 63)
+            s_w[1] = inc;
+        __syncthreads();
+        return inc - v;
+    } else {
+        if (lane == 63)
+            s_w[wave] = inc;
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t w = lane < (uint32_t)NW ? s_w[lane] : 0u;
+            uint32_t wi = w;
+#pragma unroll
+            for (int off = 1; off < NW; off <<= 1) {
+                uint32_t t = __shfl_up(wi, off, 64);
+                if (lane >= (uint32_t)off)
+                    wi += t;
+            }
+            if (lane < (uint32_t)NW)
+                s_w[lane] = wi - w;
+            if (lane == (uint32_t)NW - 1)
+                s_w[NW] = wi;
+        }
+        __syncthreads();
+        return inc - v + s_w[wave];
+    }
+}
+
+// ------------------------------------------------------------------ LDS lines
+
+// Transform (fwd or inv) every line along `axis` of the region [0,n)^3 of an
+// LDS array with pitches (1, PY, PZ), one line per thread for the first n*n
+// threads.  Lanes run along the fastest of the two other axes.
+template <typename T, int S, int n, int AXIS, bool INV, int PY, int PZ>
+__device__ __forceinline__ void lds_lines(T *lds)
+{
+    const int t = threadIdx.x;
+    if (t < n * n) {
+        const int i = t % n, j = t / n;
+        int base, stride;
+        if constexpr (AXIS == 0) {
+            base = i * PY + j * PZ;
+            stride = 1;
+        } else if constexpr (AXIS == 1) {
+            base = i + j * PZ;
+            stride = PY;
+        } else {
+            base = i + j * PY;
+            stride = PZ;
+        }
+        T v[n];
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            v[k] = lds[base + k * stride];
+        if constexpr (INV)
+            line_inv<T, S, n>(v);
+        else
+            line_fwd<T, S, n>(v);
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            lds[base + k * stride] = v[k];
+    }
+}
+
+// Forward levels n, n/2, ..., 8 of the region [0,n)^3 held in LDS.
+template <typename T, int S, int n, int PY, int PZ>
+__device__ __forceinline__ void lds_levels_fwd(T *lds)
+{
+    lds_lines<T, S, n, 0, false, PY, PZ>(lds);
+    __syncthreads();
+    lds_lines<T, S, n, 1, false, PY, PZ>(lds);
+    __syncthreads();
+    lds_lines<T, S, n, 2, false, PY, PZ>(lds);
+    __syncthreads();
+    if constexpr (n / 2 >= 8)
+        lds_levels_fwd<T, S, n / 2, PY, PZ>(lds);
+}
+
+// Inverse levels 8, 16, ..., n of the region [0,n)^3 held in LDS.
+template <typename T, int S, int n, int PY, int PZ>
+__device__ __forceinline__ void lds_levels_inv(T *lds)
+{
+    if constexpr (n / 2 >= 8)
+        lds_levels_inv<T, S, n / 2, PY, PZ>(lds);
+    lds_lines<T, S, n, 2, true, PY, PZ>(lds);
+    __syncthreads();
+    lds_lines<T, S, n, 1, true, PY, PZ>(lds);
+    __syncthreads();
+    lds_lines<T, S, n, 0, true, PY, PZ>(lds);
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ bool finite(T v)
+{
+    return __builtin_isfinite(v);
+}
+
+// ------------------------------------------------------- buffer addressing
+// Raw buffer accesses: a wave-uniform 128-bit resource (base, byte extent)
+// in SGPRs plus a 32-bit per-lane byte offset, so a row access costs one VGPR
+// of address instead of a 64-bit pair; accesses past the extent read 0 and
+// drop writes.  Cache policy NT (non-temporal) for data streamed once.
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+static constexpr int RSRC_DWORD3 = 0x00020000;  // raw buffer, gfx9 family
+static constexpr int CPOL_NT = 2;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, RSRC_DWORD3);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load(rsrc_t r, uint32_t voff);
+template <>
+__device__ __forceinline__ float buf_load<float>(rsrc_t r, uint32_t voff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, CPOL_NT));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(rsrc_t r, uint32_t voff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, CPOL_NT));
+}
+
+__device__ __forceinline__ void buf_store(float v, rsrc_t r, uint32_t voff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0, CPOL_NT);
+}
+__device__ __forceinline__ void buf_store(double v, rsrc_t r, uint32_t voff)
+{
+    using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0, CPOL_NT);
+}
+
+// --------------------------------------------------------------- geometry
+
+// N^3 block, Z z-slabs staged in LDS at a time, R z-columns per thread.
+// Thread t owns the columns (x, y_r) with x = t % N and
+// y_r = t / N + r N / R, r = 0..R-1; for a fixed z and r the workgroup's
+// threads hold N^2 / R consecutive coefficients q = x + N (y + N z), so each
+// wavefront holds 64 consecutive q: one mask word.
+template <typename T, int N, int Z, int R>
+struct Geom {
+    static constexpr int NT = N * N / R;      // threads per workgroup
+    static constexpr int YR = N / R;          // row stride between a thread's columns
+    static constexpr int H = N / 2;
+    static constexpr int PX = N + 1;          // finest-level staging: row pitch
+    static constexpr int PS = N * PX;         //                       slab pitch
+    static constexpr int QX = H + 1;          // coarse levels: row pitch
+    static constexpr int QS = H * QX;         //                slab pitch
+    static constexpr int STAGE = Z * PS;
+    static constexpr int COARSE = H * QS;
+    static constexpr int LDS_ELEMS = STAGE > COARSE ? STAGE : COARSE;
+    static constexpr int WAVES = NT / 64;     // wavefronts per workgroup
+    static constexpr int WORDS = N * N * N / 64;  // mask words per block
+    static constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
+    static_assert(N % Z == 0 && Z >= 1, "slab depth must divide the block edge");
+    static_assert(NT % 64 == 0 && N % R == 0, "a workgroup is whole wavefronts");
+    static_assert(WORDS <= NT, "one mask word per thread at most");
+    static_assert(LDS_ELEMS * sizeof(T) >= WORDS * sizeof(uint32_t), "LDS reused for word prefixes");
+    // mask word of (z, r) for wavefront w
+    static __device__ __forceinline__ int word(int z, int r, int w) { return (z * R + r) * WAVES + w; }
+};
+
+// Finest level, one slab group: every line along x (AXIS 0) or y (AXIS 1) of
+// the Z staged slabs, one line per thread per step, lanes along the other
+// in-slab axis (row pitch PX is odd, so neither access pattern conflicts).
+template <typename T, int S, int N, int Z, int NT, int PX, int PS, int AXIS, bool INV>
+__device__ __forceinline__ void stage_lines(T *lds)
+{
+#pragma unroll 1
+    for (int l = threadIdx.x; l < Z * N; l += NT) {
+        const int i = l % N, j = l / N;
+        const int base = j * PS + (AXIS == 0 ? i * PX : i);
+        constexpr int stride = AXIS == 0 ? 1 : PX;
+        T v[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            v[k] = lds[base + k * stride];
+        if constexpr (INV)
+            line_inv<T, S, N>(v);
+        else
+            line_fwd<T, S, N>(v);
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            lds[base + k * stride] = v[k];
+    }
+}
+
+// ------------------------------------------------------------------ forward
+
+template <typename T, int N, int S, int Z, int R>
+__global__ __launch_bounds__(N *N / R) void fwd_kernel(FwdArgs a)
+{
+    using G = Geom<T, N, Z, R>;
+    __shared__ T lds[G::LDS_ELEMS];
+    __shared__ uint64_t s_words[G::WORDS];
+    __shared__ uint32_t s_scan[G::WAVES + 1];
+    __shared__ uint64_t s_block;
+    __shared__ uint64_t s_off;
+
+    const int tid = threadIdx.x;
+    const int x = tid % N, yq = tid / N;
+    const uint32_t lane = lane_id();
+    const int wave = tid / 64;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;  // element offset of (x, yq) in a z-plane
+    const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);  // one z-slice of a block
+
+    while (true) {
+        if (tid == 0)
+            s_block = atomicAdd(&a.work->ticket, 1u);
+        __syncthreads();
+        const uint64_t b = s_block;
+        if (b >= a.nblocks)
+            break;
+        const uint32_t bx = (uint32_t)(b % a.nbx);
+        const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
+        const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
+        const T *blk = static_cast<const T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+
+        // load: for each z and r one coalesced row segment of N elements
+        T c[R][N];
+#pragma unroll
+        for (int z = 0; z < N; ++z) {
+            const rsrc_t zr = make_rsrc(blk + (size_t)z * plane, slab_bytes);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                c[r][z] = buf_load<T>(zr, (lane_off + (uint32_t)(r * G::YR) * a.nx) * (uint32_t)sizeof(T));
+        }
+        bool bad = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int z = 0; z < N; ++z)
+                bad |= !finite(c[r][z]);
+
+        // finest level: x- and y-lines per slab group in LDS, z in VGPRs
+#pragma unroll
+        for (int g = 0; g < N / Z; ++g) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < Z; ++j)
+                    lds[j * G::PS + (yq + r * G::YR) * G::PX + x] = c[r][g * Z + j];
+            __syncthreads();
+            stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 0, false>(lds);
+            __syncthreads();
+            stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 1, false>(lds);
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < Z; ++j)
+                    c[r][g * Z + j] = lds[j * G::PS + (yq + r * G::YR) * G::PX + x];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            line_fwd<T, S, N>(c[r]);
+
+        // coarser levels: [0, N/2)^3 in LDS
+        if constexpr (N / 2 >= 8) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int y = yq + r * G::YR;
+                if (x < G::H && y < G::H) {
+#pragma unroll
+                    for (int z = 0; z < G::H; ++z)
+                        lds[z * G::QS + y * G::QX + x] = c[r][z];
+                }
+            }
+            __syncthreads();
+            lds_levels_fwd<T, S, G::H, G::QX, G::QS>(lds);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int y = yq + r * G::YR;
+                if (x < G::H && y < G::H) {
+#pragma unroll
+                    for (int z = 0; z < G::H; ++z)
+                        c[r][z] = lds[z * G::QS + y * G::QX + x];
+                }
+            }
+        }
+
+        // decimation: keep the 4^3 corner and |c| >= eps (compared in double)
+        uint32_t keepbits[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = yq + r * G::YR;
+            keepbits[r] = 0;
+#pragma unroll
+            for (int z = 0; z < N; ++z) {
+                bad |= !finite(c[r][z]);
+                const bool keep = (z < 4 && x < 4 && y < 4) || (__builtin_fabs((double)c[r][z]) >= a.eps);
+                keepbits[r] |= (uint32_t)keep << z;
+                const uint64_t m = __ballot(keep);
+                if (lane == 0)
+                    s_words[G::word(z, r, wave)] = m;
+            }
+        }
+        if (bad)
+            atomicOr(&a.work->status, STATUS_NONFINITE);
+        __syncthreads();
+
+        // word popcounts -> exclusive prefix in q order
+        const uint32_t cnt = tid < G::WORDS ? (uint32_t)__popcll(s_words[tid]) : 0u;
+        const uint32_t pre = block_exclusive_scan<G::NT>(cnt, s_scan);
+        const uint32_t nnz = s_scan[G::WAVES];
+        uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds);  // coarse data already read back
+        if (tid < G::WORDS)
+            s_pre[tid] = pre;
+
+        const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
+        const uint64_t rbytes = (used + 15ull) & ~15ull;
+        if (tid == 0)
+            s_off = lookback(a.flags, b, rbytes, &a.work->status);
+        __syncthreads();
+        const uint64_t off = s_off;
+        uint8_t *rec = a.out + a.p0 + off;
+
+        if (tid == 0) {
+            reinterpret_cast<uint32_t *>(rec)[0] = nnz;
+            reinterpret_cast<uint32_t *>(rec)[1] = 0u;
+            a.offsets[b + 1] = off + rbytes;
+            for (uint64_t p = used; p < rbytes; p += 4)
+                *reinterpret_cast<uint32_t *>(rec + p) = 0u;
+            if (b + 1 == a.nblocks) {
+                *reinterpret_cast<uint64_t *>(a.out + 56) = off + rbytes;
+                a.work->total = a.p0 + off + rbytes;
+            }
+        }
+        uint64_t *mask = reinterpret_cast<uint64_t *>(rec + 8);
+        if (tid < G::WORDS)
+            mask[tid] = s_words[tid];
+        const rsrc_t vr = make_rsrc(rec + 8 + G::MASK_BYTES, nnz * (uint32_t)sizeof(T));
+#pragma unroll
+        for (int z = 0; z < N; ++z) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if ((keepbits[r] >> z) & 1u) {
+                    const int wi = G::word(z, r, wave);
+                    buf_store(c[r][z], vr, (s_pre[wi] + mbcnt(s_words[wi])) * (uint32_t)sizeof(T));
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ inverse
+
+template <typename T, int N, int S, int Z, int R>
+__global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
+{
+    using G = Geom<T, N, Z, R>;
+    __shared__ T lds[G::LDS_ELEMS];
+    __shared__ uint64_t s_words[G::WORDS];
+    __shared__ uint32_t s_pre[G::WORDS];
+    __shared__ uint32_t s_scan[G::WAVES + 1];
+    __shared__ uint64_t s_block;
+    __shared__ uint32_t s_ok;
+
+    const int tid = threadIdx.x;
+    const int x = tid % N, yq = tid / N;
+    const uint32_t lane = lane_id();
+    const int wave = tid / 64;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;
+    const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
+    const uint64_t *offs = reinterpret_cast<const uint64_t *>(a.in + 64);
+
+    while (true) {
+        if (tid == 0) {
+            const uint64_t b = atomicAdd(&a.work->ticket, 1u);
+            s_block = b;
+            uint32_t ok = 0;
+            if (b < a.nblocks) {
+                const uint64_t o0 = offs[b], o1 = offs[b + 1];
+                ok = o1 >= o0 && o1 <= a.payload && o1 - o0 >= 8ull + G::MASK_BYTES;
+                if (ok) {
+                    const uint32_t nnz = *reinterpret_cast<const uint32_t *>(a.in + a.p0 + o0);
+                    const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
+                    ok = nnz <= (uint32_t)(N * N * N) && ((used + 15ull) & ~15ull) == o1 - o0;
+                }
+                if (!ok)
+                    atomicOr(&a.work->status, STATUS_FORMAT);
+            }
+            s_ok = ok;
+        }
+        __syncthreads();
+        const uint64_t b = s_block;
+        if (b >= a.nblocks)
+            break;
+        if (!s_ok) {
+            __syncthreads();
+            continue;
+        }
+        const uint8_t *rec = a.in + a.p0 + offs[b];
+        const uint32_t nnz = *reinterpret_cast<const uint32_t *>(rec);
+        const uint64_t *mask = reinterpret_cast<const uint64_t *>(rec + 8);
+        const rsrc_t vr = make_rsrc(rec + 8 + G::MASK_BYTES, nnz * (uint32_t)sizeof(T));
+
+        if (tid < G::WORDS)
+            s_words[tid] = mask[tid];
+        __syncthreads();
+        const uint32_t cnt = tid < G::WORDS ? (uint32_t)__popcll(s_words[tid]) : 0u;
+        const uint32_t pre = block_exclusive_scan<G::NT>(cnt, s_scan);
+        if (tid < G::WORDS)
+            s_pre[tid] = pre;
+        __syncthreads();
+        if (s_scan[G::WAVES] != nnz) {
+            if (tid == 0)
+                atomicOr(&a.work->status, STATUS_FORMAT);
+            __syncthreads();
+            continue;
+        }
+
+        // gather: kept coefficient q -> vals[rank(q)], dropped -> +0
+        T c[R][N];
+#pragma unroll
+        for (int z = 0; z < N; ++z) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int wi = G::word(z, r, wave);
+                const uint64_t m = s_words[wi];
+                c[r][z] = T(0);
+                if ((m >> lane) & 1ull)
+                    c[r][z] = buf_load<T>(vr, (s_pre[wi] + mbcnt(m)) * (uint32_t)sizeof(T));
+            }
+        }
+
+        // coarser levels 8 .. N/2 in LDS
+        if constexpr (N / 2 >= 8) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int y = yq + r * G::YR;
+                if (x < G::H && y < G::H) {
+#pragma unroll
+                    for (int z = 0; z < G::H; ++z)
+                        lds[z * G::QS + y * G::QX + x] = c[r][z];
+                }
+            }
+            __syncthreads();
+            lds_levels_inv<T, S, G::H, G::QX, G::QS>(lds);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int y = yq + r * G::YR;
+                if (x < G::H && y < G::H) {
+#pragma unroll
+                    for (int z = 0; z < G::H; ++z)
+                        c[r][z] = lds[z * G::QS + y * G::QX + x];
+                }
+            }
+            __syncthreads();
+        }
+
+        // finest level: z in VGPRs, then y- and x-lines per slab group
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            line_inv<T, S, N>(c[r]);
+        const uint32_t bx = (uint32_t)(b % a.nbx);
+        const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
+        const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
+        T *blk = static_cast<T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+#pragma unroll
+        for (int g = 0; g < N / Z; ++g) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < Z; ++j)
+                    lds[j * G::PS + (yq + r * G::YR) * G::PX + x] = c[r][g * Z + j];
+            __syncthreads();
+            stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 1, true>(lds);
+            __syncthreads();
+            stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 0, true>(lds);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < Z; ++j) {
+                const rsrc_t zr = make_rsrc(blk + (size_t)(g * Z + j) * plane, slab_bytes);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    buf_store(lds[j * G::PS + (yq + r * G::YR) * G::PX + x], zr,
+                              (lane_off + (uint32_t)(r * G::YR) * a.nx) * (uint32_t)sizeof(T));
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------- bookkeeping
+
+// Reset the ticket and status, clear the look-back flags, write the header
+// (payload size 0 until the last block fills it), off[0] and the zero pad
+// between the offset table and the payload.
+__global__ void prep_fwd_kernel(PrepArgs a)
+{
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = i0; i < a.nblocks; i += stride)
+        a.flags[i] = 0;
+    if (i0 == 0) {
+        a.work->ticket = 0;
+        a.work->status = 0;
+        a.work->total = a.nblocks == 0 ? a.p0 : 0;
+        uint32_t *h = reinterpret_cast<uint32_t *>(a.out);
+        for (int k = 0; k < 16; ++k)
+            h[k] = a.header[k];
+        reinterpret_cast<uint64_t *>(a.out + 64)[0] = 0;
+    }
+    const uint64_t pad0 = 64 + 8 * (a.nblocks + 1);
+    for (uint64_t p = pad0 + 4 * i0; p < a.p0; p += 4 * stride)
+        *reinterpret_cast<uint32_t *>(a.out + p) = 0u;
+}
+
+__global__ void prep_inv_kernel(CzWork *work)
+{
+    if (threadIdx.x == 0) {
+        work->ticket = 0;
+        work->status = 0;
+    }
+}
+
+// ----------------------------------------------------------------- dispatch
+
+// Shape per (precision, N): slab depth Z and columns per thread R.  Float
+// blocks and double blocks up to 16^3 are staged whole in LDS with one column
+// per thread; a double 32^3 block (256 KiB) is staged 16 slabs at a time
+// (132 KiB of the 160 KiB LDS) with two columns per thread, so the 512-thread
+// workgroup has 256 VGPRs per lane for the half-block it keeps in registers.
+template <typename T, int N>
+struct Shape {
+    static constexpr bool big = sizeof(T) == 8 && N >= 32;
+    static constexpr int Z = big ? N / 2 : N;
+    static constexpr int R = big ? 2 : 1;
+};
+
+template <typename T, int N, int S>
+static hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t st)
+{
+    using P = Shape<T, N>;
+    hipLaunchKernelGGL((fwd_kernel<T, N, S, P::Z, P::R>), dim3(grid), dim3(N * N / P::R), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int N, int S>
+static hipError_t launch_inv_t(const InvArgs &a, int grid, hipStream_t st)
+{
+    using P = Shape<T, N>;
+    hipLaunchKernelGGL((inv_kernel<T, N, S, P::Z, P::R>), dim3(grid), dim3(N * N / P::R), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int N, int S>
+static int occupancy_t(bool inverse)
+{
+    using P = Shape<T, N>;
+    int nb = 0;
+    hipError_t e =
+        inverse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, inv_kernel<T, N, S, P::Z, P::R>, N * N / P::R, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<T, N, S, P::Z, P::R>, N * N / P::R, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+int threads_per_block(const KernelKey &key)
+{
+    const bool big = key.elem_bytes == 8 && key.block >= 32;
+    return (int)(key.block * key.block) / (big ? 2 : 1);
+}
+
+#define CZ_DISPATCH(T, OP, ARGS)                                                                              \
+    switch (key.block) {                                                                                     \
+    case 8:                                                                                                  \
+        switch (key.scheme) {                                                                                \
+        case W4: return OP<T, 8, W4> ARGS;                                           \
+        case W4LI: return OP<T, 8, W4LI> ARGS;                                       \
+        default: return OP<T, 8, W3AI> ARGS;                                         \
+        }                                                                                                    \
+    case 16:                                                                                                 \
+        switch (key.scheme) {                                                                                \
+        case W4: return OP<T, 16, W4> ARGS;                                         \
+        case W4LI: return OP<T, 16, W4LI> ARGS;                                     \
+        default: return OP<T, 16, W3AI> ARGS;                                       \
+        }                                                                                                    \
+    default:                                                                                                 \
+        switch (key.scheme) {                                                                                \
+        case W4: return OP<T, 32, W4> ARGS;                                         \
+        case W4LI: return OP<T, 32, W4LI> ARGS;                                     \
+        default: return OP<T, 32, W3AI> ARGS;                                       \
+        }                                                                                                    \
+    }
+
+hipError_t launch_fwd(const KernelKey &key, const FwdArgs &a, int grid, hipStream_t st)
+{
+    if (key.elem_bytes == 4) {
+        CZ_DISPATCH(float, launch_fwd_t, (a, grid, st))
+    } else {
+        CZ_DISPATCH(double, launch_fwd_t, (a, grid, st))
+    }
+}
+
+hipError_t launch_inv(const KernelKey &key, const InvArgs &a, int grid, hipStream_t st)
+{
+    if (key.elem_bytes == 4) {
+        CZ_DISPATCH(float, launch_inv_t, (a, grid, st))
+    } else {
+        CZ_DISPATCH(double, launch_inv_t, (a, grid, st))
+    }
+}
+
+int occupancy(const KernelKey &key, bool inverse)
+{
+    if (key.elem_bytes == 4) {
+        CZ_DISPATCH(float, occupancy_t, (inverse))
+    } else {
+        CZ_DISPATCH(double, occupancy_t, (inverse))
+    }
+}
+
+hipError_t launch_prep_fwd(const PrepArgs &a, hipStream_t st)
+{
+    uint64_t need = a.nblocks > 0 ? a.nblocks : 1;
+    int grid = (int)((need + 255) / 256);
+    if (grid > 1024)
+        grid = 1024;
+    hipLaunchKernelGGL(prep_fwd_kernel, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_inv(CzWork *work, hipStream_t st)
+{
+    hipLaunchKernelGGL(prep_inv_kernel, dim3(1), dim3(64), 0, st, work);
+    return hipGetLastError();
+}
+
+}  // namespace czk

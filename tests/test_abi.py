@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports every entry point include/cz.h
+declares; host-only entry points (no GPU needed) behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cz.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cz_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def czlib():
+    from paper_1903_07761_amd import _cz
+
+    return _cz
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("cz_create", "cz_destroy", "cz_reserve", "cz_compress_bound", "cz_compress", "cz_decompress",
+                 "cz_get_status", "cz_read_header", "cz_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(czlib):
+    L = czlib.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_compress_bound_matches_layout(czlib):
+    p = czlib.params(64, 64, 64, 32, "W4", 4, 0.1)
+    # 8 blocks: payload start roundup16(64 + 8 * 9) = 144; record roundup16(8 + 4096 + 32768 * 4)
+    assert czlib.compress_bound(p) == 144 + 8 * 135184
+    p = czlib.params(32, 16, 48, 16, "W3_ai", 8, 0.0)
+    nb = 2 * 1 * 3
+    assert czlib.compress_bound(p) == (64 + 8 * (nb + 1) + 15) // 16 * 16 + nb * ((8 + 512 + 4096 * 8 + 15) // 16 * 16)
+
+
+def test_compress_bound_agrees_with_oracle(czlib, oracle):
+    for shape, N, elem in [((32, 32, 32), 8, 4), ((64, 32, 96), 32, 8), ((16, 16, 16), 16, 4), ((0, 32, 32), 32, 4)]:
+        nz, ny, nx = shape
+        assert czlib.compress_bound(czlib.params(nx, ny, nz, N, 0, elem, 0.0)) == oracle.compress_bound(shape, N, elem)
+
+
+def test_invalid_params_give_zero_bound(czlib):
+    assert czlib.compress_bound(czlib.params(40, 32, 32, 32, 0, 4, 0.1)) == 0  # not a multiple
+    assert czlib.compress_bound(czlib.params(32, 32, 32, 12, 0, 4, 0.1)) == 0  # not a power of two
+    assert czlib.compress_bound(czlib.params(32, 32, 32, 32, 3, 4, 0.1)) == 0  # bad scheme
+    assert czlib.compress_bound(czlib.params(32, 32, 32, 32, 0, 2, 0.1)) == 0  # bad element size
+    assert czlib.compress_bound(czlib.params(32, 32, 32, 32, 0, 4, -1.0)) == 0  # eps < 0
+    assert czlib.compress_bound(czlib.params(32, 32, 32, 32, 0, 4, float("nan"))) == 0
+
+
+def test_read_header_parses_oracle_stream(czlib, oracle):
+    import numpy as np
+
+    f = np.ones((32, 16, 48), np.float64)
+    s = oracle.compress(f, 16, "W4_li", 0.25)
+    p, nb, total = czlib.read_header(s[:64])
+    assert (p.nx, p.ny, p.nz, p.block, p.scheme, p.elem_bytes, p.epsilon) == (48, 16, 32, 16, 1, 8, 0.25)
+    assert nb == 6 and total == len(s)
+    bad = bytearray(s[:64])
+    bad[0] = ord("X")
+    with pytest.raises(czlib.CzError) as e:
+        czlib.read_header(bytes(bad))
+    assert e.value.code == czlib.ERR_FORMAT
+
+
+def test_strerror(czlib):
+    assert czlib.strerror(0) == "ok"
+    assert "stream" in czlib.strerror(czlib.ERR_FORMAT)
