@@ -76,7 +76,9 @@ int check_params(const cz_params *p, uint64_t *nblocks)
     if ((uint64_t)p->nx * N * p->elem_bytes >= (1ull << 31))
         return CZ_ERR_SHAPE;
     const uint64_t nb = (uint64_t)(p->nx / N) * (p->ny / N) * (p->nz / N);
-    if (nb >= MAX_BLOCKS)
+    // one workgroup of N^2 (or N^2 / 2) threads per block: the grid's thread
+    // count must stay below 2^32
+    if (nb >= MAX_BLOCKS || nb * N * N >= (1ull << 32))
         return CZ_ERR_SHAPE;
     *nblocks = nb;
     return CZ_OK;
@@ -277,7 +279,11 @@ int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_ou
         fa.nblocks = nb;
         fa.p0 = pa.p0;
         fa.eps = p->epsilon;
-        if (czk::launch_fwd(key, fa, grid_for(ctx, key, false, nb), st) != hipSuccess)
+        fa.eps_f = (float)p->epsilon;  // round to nearest, then up if it fell below
+        if ((double)fa.eps_f < p->epsilon)
+            fa.eps_f = std::nextafter(fa.eps_f, INFINITY);
+        // one workgroup per block (the forward kernel is not persistent)
+        if (czk::launch_fwd(key, fa, (int)nb, st) != hipSuccess)
             return CZ_ERR_HIP;
     }
     if (d_out_bytes &&

@@ -36,6 +36,7 @@ struct FwdArgs {
     uint64_t nblocks;
     uint64_t p0;         // payload start
     double eps;
+    float eps_f;         // smallest float >= eps (the same test for float data)
 };
 
 struct InvArgs {

@@ -92,6 +92,17 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also releases
+// global memory, which costs a wait for every load and store still in flight;
+// all communication between the threads of a workgroup here goes through LDS,
+// so in-flight global accesses may stay in flight across this barrier.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Exclusive scan of one u32 per thread over a workgroup of NT threads.
 // s_w must hold NT/64 + 1 words; the total lands in s_w[NT/64].
 template <int NT>
@@ -110,12 +121,12 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     if constexpr (NW == 1) {
         if (lane == 63)
             s_w[1] = inc;
-        __syncthreads();
+        lds_barrier();
         return inc - v;
     } else {
         if (lane == 63)
             s_w[wave] = inc;
-        __syncthreads();
+        lds_barrier();
         if (wave == 0) {
             uint32_t w = lane < (uint32_t)NW ? s_w[lane] : 0u;
             uint32_t wi = w;
@@ -130,7 +141,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
             if (lane == (uint32_t)NW - 1)
                 s_w[NW] = wi;
         }
-        __syncthreads();
+        lds_barrier();
         return inc - v + s_w[wave];
     }
 }
@@ -176,11 +187,11 @@ template <typename T, int S, int n, int PY, int PZ>
 __device__ __forceinline__ void lds_levels_fwd(T *lds)
 {
     lds_lines<T, S, n, 0, false, PY, PZ>(lds);
-    __syncthreads();
+    lds_barrier();
     lds_lines<T, S, n, 1, false, PY, PZ>(lds);
-    __syncthreads();
+    lds_barrier();
     lds_lines<T, S, n, 2, false, PY, PZ>(lds);
-    __syncthreads();
+    lds_barrier();
     if constexpr (n / 2 >= 8)
         lds_levels_fwd<T, S, n / 2, PY, PZ>(lds);
 }
@@ -192,11 +203,11 @@ __device__ __forceinline__ void lds_levels_inv(T *lds)
     if constexpr (n / 2 >= 8)
         lds_levels_inv<T, S, n / 2, PY, PZ>(lds);
     lds_lines<T, S, n, 2, true, PY, PZ>(lds);
-    __syncthreads();
+    lds_barrier();
     lds_lines<T, S, n, 1, true, PY, PZ>(lds);
-    __syncthreads();
+    lds_barrier();
     lds_lines<T, S, n, 0, true, PY, PZ>(lds);
-    __syncthreads();
+    lds_barrier();
 }
 
 template <typename T>
@@ -245,12 +256,15 @@ __device__ __forceinline__ void buf_store(double v, rsrc_t r, uint32_t voff)
 
 // --------------------------------------------------------------- geometry
 
-// N^3 block, Z z-slabs staged in LDS at a time, R z-columns per thread.
+// N^3 block, Z z-slabs staged in LDS at a time, R z-columns per thread, and
+// (forward) ZP z-planes kept in VGPRs after the finest level: planes
+// [ZP, N) -- final level-1 details -- are parked in the LDS the staging
+// frees, behind the coarse region.
 // Thread t owns the columns (x, y_r) with x = t % N and
 // y_r = t / N + r N / R, r = 0..R-1; for a fixed z and r the workgroup's
 // threads hold N^2 / R consecutive coefficients q = x + N (y + N z), so each
 // wavefront holds 64 consecutive q: one mask word.
-template <typename T, int N, int Z, int R>
+template <typename T, int N, int Z, int R, int ZP = N>
 struct Geom {
     static constexpr int NT = N * N / R;      // threads per workgroup
     static constexpr int YR = N / R;          // row stride between a thread's columns
@@ -261,14 +275,16 @@ struct Geom {
     static constexpr int QS = H * QX;         //                slab pitch
     static constexpr int STAGE = Z * PS;
     static constexpr int COARSE = H * QS;
-    static constexpr int LDS_ELEMS = STAGE > COARSE ? STAGE : COARSE;
+    static constexpr int PARK = (N - ZP) * PS;  // parked planes, staging pitches
+    static constexpr int LDS_ELEMS = STAGE > COARSE + PARK ? STAGE : COARSE + PARK;
     static constexpr int WAVES = NT / 64;     // wavefronts per workgroup
     static constexpr int WORDS = N * N * N / 64;  // mask words per block
     static constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
     static_assert(N % Z == 0 && Z >= 1, "slab depth must divide the block edge");
     static_assert(NT % 64 == 0 && N % R == 0, "a workgroup is whole wavefronts");
     static_assert(WORDS <= NT, "one mask word per thread at most");
-    static_assert(LDS_ELEMS * sizeof(T) >= WORDS * sizeof(uint32_t), "LDS reused for word prefixes");
+    static_assert(COARSE * sizeof(T) >= WORDS * sizeof(uint32_t), "coarse area reused for word prefixes");
+    static_assert(ZP >= H && ZP <= N, "the coarse region stays in VGPRs");
     // mask word of (z, r) for wavefront w
     static __device__ __forceinline__ int word(int z, int r, int w) { return (z * R + r) * WAVES + w; }
 };
@@ -300,10 +316,49 @@ __device__ __forceinline__ void stage_lines(T *lds)
 
 // ------------------------------------------------------------------ forward
 
-template <typename T, int N, int S, int Z, int R>
-__global__ __launch_bounds__(N *N / R) void fwd_kernel(FwdArgs a)
+// Decimation test |c| >= eps in double.  For float data this equals
+// |c| >= eps_f with eps_f the smallest float >= eps (computed on the host).
+template <typename T>
+__device__ __forceinline__ bool keep_test(T v, const FwdArgs &a);
+template <>
+__device__ __forceinline__ bool keep_test<float>(float v, const FwdArgs &a)
+{
+    return __builtin_fabsf(v) >= a.eps_f;
+}
+template <>
+__device__ __forceinline__ bool keep_test<double>(double v, const FwdArgs &a)
+{
+    return __builtin_fabs(v) >= a.eps;
+}
+
+// Issue the loads of slab group g of block b: planes [g Z, g Z + Z), one
+// coalesced row segment per plane and column.
+template <typename T, int N, int Z, int R>
+__device__ __forceinline__ void load_planes(const FwdArgs &a, uint64_t b, int g, uint32_t lane_off, T (*dst)[N])
 {
     using G = Geom<T, N, Z, R>;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const uint32_t bx = (uint32_t)(b % a.nbx);
+    const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
+    const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
+    const T *blk = static_cast<const T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+    const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int j = 0; j < Z; ++j) {
+        const rsrc_t zr = make_rsrc(blk + (size_t)(g * Z + j) * plane, slab_bytes);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            dst[r][g * Z + j] = buf_load<T>(zr, (lane_off + (uint32_t)(r * G::YR) * a.nx) * (uint32_t)sizeof(T));
+    }
+}
+
+// One workgroup per block: the block's ticket is taken at workgroup start,
+// so every smaller ticket belongs to a workgroup that is resident or done and
+// the look-back always completes.
+template <typename T, int N, int S, int Z, int R, int ZP>
+__global__ __launch_bounds__(N *N / R) void fwd_kernel(FwdArgs a)
+{
+    using G = Geom<T, N, Z, R, ZP>;
     __shared__ T lds[G::LDS_ELEMS];
     __shared__ uint64_t s_words[G::WORDS];
     __shared__ uint32_t s_scan[G::WAVES + 1];
@@ -314,66 +369,63 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(FwdArgs a)
     const int x = tid % N, yq = tid / N;
     const uint32_t lane = lane_id();
     const int wave = tid / 64;
-    const size_t plane = (size_t)a.nx * a.ny;
     const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;  // element offset of (x, yq) in a z-plane
-    const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);  // one z-slice of a block
 
-    while (true) {
-        if (tid == 0)
-            s_block = atomicAdd(&a.work->ticket, 1u);
-        __syncthreads();
-        const uint64_t b = s_block;
-        if (b >= a.nblocks)
-            break;
-        const uint32_t bx = (uint32_t)(b % a.nbx);
-        const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
-        const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
-        const T *blk = static_cast<const T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+    if (tid == 0)
+        s_block = atomicAdd(&a.work->ticket, 1u);
+    lds_barrier();
+    const uint64_t b = s_block;
+    if (b >= a.nblocks)
+        return;
 
-        // load: for each z and r one coalesced row segment of N elements
-        T c[R][N];
+    // load: for each z and r one coalesced row segment of N elements; the
+    // rows of slab group g+1 stay in flight while group g is transformed
+    T c[R][N];
+    bool bad = false;
+    load_planes<T, N, Z, R>(a, b, 0, lane_off, c);
+
+    // finest level: x- and y-lines per slab group in LDS, z in VGPRs
 #pragma unroll
-        for (int z = 0; z < N; ++z) {
-            const rsrc_t zr = make_rsrc(blk + (size_t)z * plane, slab_bytes);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                c[r][z] = buf_load<T>(zr, (lane_off + (uint32_t)(r * G::YR) * a.nx) * (uint32_t)sizeof(T));
-        }
-        bool bad = false;
+    for (int g = 0; g < N / Z; ++g) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int z = 0; z < N; ++z)
-                bad |= !finite(c[r][z]);
-
-        // finest level: x- and y-lines per slab group in LDS, z in VGPRs
-#pragma unroll
-        for (int g = 0; g < N / Z; ++g) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int j = 0; j < Z; ++j)
-                    lds[j * G::PS + (yq + r * G::YR) * G::PX + x] = c[r][g * Z + j];
-            __syncthreads();
-            stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 0, false>(lds);
-            __syncthreads();
-            stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 1, false>(lds);
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int j = 0; j < Z; ++j)
-                    c[r][g * Z + j] = lds[j * G::PS + (yq + r * G::YR) * G::PX + x];
-            __syncthreads();
-        }
+            for (int j = 0; j < Z; ++j) {
+                bad |= !finite(c[r][g * Z + j]);
+                lds[j * G::PS + (yq + r * G::YR) * G::PX + x] = c[r][g * Z + j];
+            }
+        if (g + 1 < N / Z)
+            load_planes<T, N, Z, R>(a, b, g + 1, lane_off, c);
+        lds_barrier();
+        stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 0, false>(lds);
+        lds_barrier();
+        stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 1, false>(lds);
+        lds_barrier();
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            line_fwd<T, S, N>(c[r]);
-
-        // coarser levels: [0, N/2)^3 in LDS
-        if constexpr (N / 2 >= 8) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
+            for (int j = 0; j < Z; ++j)
+                c[r][g * Z + j] = lds[j * G::PS + (yq + r * G::YR) * G::PX + x];
+        lds_barrier();
+    }
+    // z-lines of the finest level, one column at a time; planes [ZP, N)
+    // (final level-1 details) are parked in LDS right away
+    T *park = lds + G::COARSE;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        __builtin_amdgcn_sched_barrier(0);
+        line_fwd<T, S, N>(c[r]);
+#pragma unroll
+        for (int z = ZP; z < N; ++z)
+            park[(z - ZP) * G::PS + (yq + r * G::YR) * G::PX + x] = c[r][z];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // coarser levels: [0, N/2)^3 in LDS (only columns with y < N/2 take part)
+    if constexpr (N / 2 >= 8) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r * G::YR < G::H) {
                 const int y = yq + r * G::YR;
                 if (x < G::H && y < G::H) {
 #pragma unroll
@@ -381,81 +433,113 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(FwdArgs a)
                         lds[z * G::QS + y * G::QX + x] = c[r][z];
                 }
             }
-            __syncthreads();
-            lds_levels_fwd<T, S, G::H, G::QX, G::QS>(lds);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int y = yq + r * G::YR;
-                if (x < G::H && y < G::H) {
-#pragma unroll
-                    for (int z = 0; z < G::H; ++z)
-                        c[r][z] = lds[z * G::QS + y * G::QX + x];
-                }
-            }
         }
-
-        // decimation: keep the 4^3 corner and |c| >= eps (compared in double)
-        uint32_t keepbits[R];
+        lds_barrier();
+        lds_levels_fwd<T, S, G::H, G::QX, G::QS>(lds);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int y = yq + r * G::YR;
-            keepbits[r] = 0;
+            if (r * G::YR < G::H) {
+                const int y = yq + r * G::YR;
+                const bool in = x < G::H && y < G::H;
+                const int base = in ? y * G::QX + x : 0;
 #pragma unroll
-            for (int z = 0; z < N; ++z) {
-                bad |= !finite(c[r][z]);
-                const bool keep = (z < 4 && x < 4 && y < 4) || (__builtin_fabs((double)c[r][z]) >= a.eps);
-                keepbits[r] |= (uint32_t)keep << z;
-                const uint64_t m = __ballot(keep);
-                if (lane == 0)
-                    s_words[G::word(z, r, wave)] = m;
-            }
-        }
-        if (bad)
-            atomicOr(&a.work->status, STATUS_NONFINITE);
-        __syncthreads();
-
-        // word popcounts -> exclusive prefix in q order
-        const uint32_t cnt = tid < G::WORDS ? (uint32_t)__popcll(s_words[tid]) : 0u;
-        const uint32_t pre = block_exclusive_scan<G::NT>(cnt, s_scan);
-        const uint32_t nnz = s_scan[G::WAVES];
-        uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds);  // coarse data already read back
-        if (tid < G::WORDS)
-            s_pre[tid] = pre;
-
-        const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
-        const uint64_t rbytes = (used + 15ull) & ~15ull;
-        if (tid == 0)
-            s_off = lookback(a.flags, b, rbytes, &a.work->status);
-        __syncthreads();
-        const uint64_t off = s_off;
-        uint8_t *rec = a.out + a.p0 + off;
-
-        if (tid == 0) {
-            reinterpret_cast<uint32_t *>(rec)[0] = nnz;
-            reinterpret_cast<uint32_t *>(rec)[1] = 0u;
-            a.offsets[b + 1] = off + rbytes;
-            for (uint64_t p = used; p < rbytes; p += 4)
-                *reinterpret_cast<uint32_t *>(rec + p) = 0u;
-            if (b + 1 == a.nblocks) {
-                *reinterpret_cast<uint64_t *>(a.out + 56) = off + rbytes;
-                a.work->total = a.p0 + off + rbytes;
-            }
-        }
-        uint64_t *mask = reinterpret_cast<uint64_t *>(rec + 8);
-        if (tid < G::WORDS)
-            mask[tid] = s_words[tid];
-        const rsrc_t vr = make_rsrc(rec + 8 + G::MASK_BYTES, nnz * (uint32_t)sizeof(T));
-#pragma unroll
-        for (int z = 0; z < N; ++z) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if ((keepbits[r] >> z) & 1u) {
-                    const int wi = G::word(z, r, wave);
-                    buf_store(c[r][z], vr, (s_pre[wi] + mbcnt(s_words[wi])) * (uint32_t)sizeof(T));
+                for (int z = 0; z < G::H; ++z) {
+                    const T v = lds[z * G::QS + base];
+                    c[r][z] = in ? v : c[r][z];
                 }
             }
         }
-        __syncthreads();
+    }
+
+    // decimation: keep the 4^3 corner and |c| >= eps (compared in double)
+    uint32_t keepbits[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = yq + r * G::YR;
+        uint32_t kb = 0;
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) {
+            const T v = c[r][z];
+            bad |= !finite(v);
+            const bool keep = (z < 4 && x < 4 && y < 4) || keep_test<T>(v, a);
+            kb |= (uint32_t)keep << z;
+        }
+        const T *pk = park + y * G::PX + x;
+#pragma unroll
+        for (int z = ZP; z < N; ++z) {
+            const T v = pk[(z - ZP) * G::PS];
+            bad |= !finite(v);
+            kb |= (uint32_t)keep_test<T>(v, a) << z;
+        }
+        keepbits[r] = kb;
+    }
+    if (bad)
+        atomicOr(&a.work->status, STATUS_NONFINITE);
+    // mask words: lane z R + r of each wavefront keeps the ballot of (z, r)
+    uint64_t myword = 0;
+#pragma unroll
+    for (int z = 0; z < N; ++z) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t m = __ballot((keepbits[r] >> z) & 1u);
+            myword = lane == (uint32_t)(z * R + r) ? m : myword;
+        }
+    }
+    if (lane < (uint32_t)(N * R))
+        s_words[(int)lane * G::WAVES + wave] = myword;
+    lds_barrier();
+
+    // word popcounts -> exclusive prefix in q order
+    const uint32_t cnt = tid < G::WORDS ? (uint32_t)__popcll(s_words[tid]) : 0u;
+    const uint32_t pre = block_exclusive_scan<G::NT>(cnt, s_scan);
+    const uint32_t nnz = s_scan[G::WAVES];
+    uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds);  // coarse data already read back
+    if (tid < G::WORDS)
+        s_pre[tid] = pre;
+
+    const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
+    const uint64_t rbytes = (used + 15ull) & ~15ull;
+    if (tid == 0)
+        s_off = lookback(a.flags, b, rbytes, &a.work->status);
+    lds_barrier();
+    const uint64_t off = s_off;
+    uint8_t *rec = a.out + a.p0 + off;
+
+    if (tid == 0) {
+        reinterpret_cast<uint32_t *>(rec)[0] = nnz;
+        reinterpret_cast<uint32_t *>(rec)[1] = 0u;
+        a.offsets[b + 1] = off + rbytes;
+        for (uint64_t p = used; p < rbytes; p += 4)
+            *reinterpret_cast<uint32_t *>(rec + p) = 0u;
+        if (b + 1 == a.nblocks) {
+            *reinterpret_cast<uint64_t *>(a.out + 56) = off + rbytes;
+            a.work->total = a.p0 + off + rbytes;
+        }
+    }
+    uint64_t *mask = reinterpret_cast<uint64_t *>(rec + 8);
+    if (tid < G::WORDS)
+        mask[tid] = s_words[tid];
+    const rsrc_t vr = make_rsrc(rec + 8 + G::MASK_BYTES, nnz * (uint32_t)sizeof(T));
+#pragma unroll
+    for (int z = 0; z < ZP; ++z) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if ((keepbits[r] >> z) & 1u) {
+                const int wi = G::word(z, r, wave);
+                buf_store(c[r][z], vr, (s_pre[wi] + mbcnt(s_words[wi])) * (uint32_t)sizeof(T));
+            }
+        }
+    }
+#pragma unroll
+    for (int z = ZP; z < N; ++z) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if ((keepbits[r] >> z) & 1u) {
+                const int wi = G::word(z, r, wave);
+                const T v = park[(z - ZP) * G::PS + (yq + r * G::YR) * G::PX + x];
+                buf_store(v, vr, (s_pre[wi] + mbcnt(s_words[wi])) * (uint32_t)sizeof(T));
+            }
+        }
     }
 }
 
@@ -499,12 +583,12 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
             }
             s_ok = ok;
         }
-        __syncthreads();
+        lds_barrier();
         const uint64_t b = s_block;
         if (b >= a.nblocks)
             break;
         if (!s_ok) {
-            __syncthreads();
+            lds_barrier();
             continue;
         }
         const uint8_t *rec = a.in + a.p0 + offs[b];
@@ -514,16 +598,16 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
 
         if (tid < G::WORDS)
             s_words[tid] = mask[tid];
-        __syncthreads();
+        lds_barrier();
         const uint32_t cnt = tid < G::WORDS ? (uint32_t)__popcll(s_words[tid]) : 0u;
         const uint32_t pre = block_exclusive_scan<G::NT>(cnt, s_scan);
         if (tid < G::WORDS)
             s_pre[tid] = pre;
-        __syncthreads();
+        lds_barrier();
         if (s_scan[G::WAVES] != nnz) {
             if (tid == 0)
                 atomicOr(&a.work->status, STATUS_FORMAT);
-            __syncthreads();
+            lds_barrier();
             continue;
         }
 
@@ -552,7 +636,7 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
                         lds[z * G::QS + y * G::QX + x] = c[r][z];
                 }
             }
-            __syncthreads();
+            lds_barrier();
             lds_levels_inv<T, S, G::H, G::QX, G::QS>(lds);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -563,7 +647,7 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
                         c[r][z] = lds[z * G::QS + y * G::QX + x];
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
 
         // finest level: z in VGPRs, then y- and x-lines per slab group
@@ -581,11 +665,11 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
 #pragma unroll
                 for (int j = 0; j < Z; ++j)
                     lds[j * G::PS + (yq + r * G::YR) * G::PX + x] = c[r][g * Z + j];
-            __syncthreads();
+            lds_barrier();
             stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 1, true>(lds);
-            __syncthreads();
+            lds_barrier();
             stage_lines<T, S, N, Z, G::NT, G::PX, G::PS, 0, true>(lds);
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int j = 0; j < Z; ++j) {
                 const rsrc_t zr = make_rsrc(blk + (size_t)(g * Z + j) * plane, slab_bytes);
@@ -594,7 +678,7 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
                     buf_store(lds[j * G::PS + (yq + r * G::YR) * G::PX + x], zr,
                               (lane_off + (uint32_t)(r * G::YR) * a.nx) * (uint32_t)sizeof(T));
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
 }
@@ -644,13 +728,17 @@ struct Shape {
     static constexpr bool big = sizeof(T) == 8 && N >= 32;
     static constexpr int Z = big ? N / 2 : N;
     static constexpr int R = big ? 2 : 1;
+    // forward: planes kept in VGPRs after the finest level (the rest parked in
+    // LDS): double 32^3 parks 14 planes (118 KiB + 35 KiB coarse region), float
+    // 32^3 parks 16 (66 KiB + 17 KiB); smaller blocks park nothing
+    static constexpr int ZP = N < 32 ? N : (big ? N / 2 + 2 : N / 2);
 };
 
 template <typename T, int N, int S>
 static hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t st)
 {
     using P = Shape<T, N>;
-    hipLaunchKernelGGL((fwd_kernel<T, N, S, P::Z, P::R>), dim3(grid), dim3(N * N / P::R), 0, st, a);
+    hipLaunchKernelGGL((fwd_kernel<T, N, S, P::Z, P::R, P::ZP>), dim3(grid), dim3(N * N / P::R), 0, st, a);
     return hipGetLastError();
 }
 
@@ -669,7 +757,7 @@ static int occupancy_t(bool inverse)
     int nb = 0;
     hipError_t e =
         inverse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, inv_kernel<T, N, S, P::Z, P::R>, N * N / P::R, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<T, N, S, P::Z, P::R>, N * N / P::R, 0);
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<T, N, S, P::Z, P::R, P::ZP>, N * N / P::R, 0);
     return e == hipSuccess ? nb : 0;
 }
 
