@@ -47,6 +47,9 @@
  *   in the 4^3 coarse corner or (double)|c_q| >= eps; dropped values decode
  *   as +0.0.
  *
+ * Blocks up to 32^3 stay on chip (VGPRs + LDS); 64^3 blocks (1 MiB float,
+ * 2 MiB double) are staged in a per-workgroup scratch slot the context owns.
+ *
  * Conventions.  Every pointer named d_* is device memory of the context's
  * device, owned by the caller; the library keeps none of them after a call
  * returns, and never allocates on the compress/decompress paths once the
@@ -71,7 +74,8 @@ enum { CZ_W4 = 0, CZ_W4_LI = 1, CZ_W3_AI = 2 };
 enum {
     CZ_OK = 0,
     CZ_ERR_ARG = -1,       /* null pointer, bad enum, eps < 0 or non-finite   */
-    CZ_ERR_SHAPE = -2,     /* N not in {8,16,32,64} or an edge not a multiple */
+    CZ_ERR_SHAPE = -2,     /* N not in {8,16,32,64}, an edge not a multiple,  */
+                           /* or a grid too large for 32-bit block addressing */
     CZ_ERR_CAPACITY = -3,  /* output buffer too small (required size returned) */
     CZ_ERR_NONFINITE = -4, /* non-finite input or coefficient; output undefined */
     CZ_ERR_FORMAT = -5,    /* corrupt or inconsistent stream                   */

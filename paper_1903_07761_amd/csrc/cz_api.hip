@@ -21,6 +21,8 @@ struct cz_ctx {
     uint64_t *flags = nullptr;    // device: look-back flags
     uint64_t cap_blocks = 0;
     czk::CzWork *pinned = nullptr;  // host-pinned mirror of *work for sync reads
+    void *scratch = nullptr;        // N = 64 blocks: one slot per resident workgroup
+    size_t scratch_bytes = 0;
 };
 
 namespace {
@@ -56,7 +58,7 @@ int ilog2(uint32_t n)
     return l;
 }
 
-bool supported_block(uint32_t n) { return n == 8 || n == 16 || n == 32; }
+bool supported_block(uint32_t n) { return n == 8 || n == 16 || n == 32 || n == 64; }
 
 // Shared validation of a parameter block; fills nblocks on success.
 int check_params(const cz_params *p, uint64_t *nblocks)
@@ -76,9 +78,9 @@ int check_params(const cz_params *p, uint64_t *nblocks)
     if ((uint64_t)p->nx * N * p->elem_bytes >= (1ull << 31))
         return CZ_ERR_SHAPE;
     const uint64_t nb = (uint64_t)(p->nx / N) * (p->ny / N) * (p->nz / N);
-    // one workgroup of N^2 (or N^2 / 2) threads per block: the grid's thread
-    // count must stay below 2^32
-    if (nb >= MAX_BLOCKS || nb * N * N >= (1ull << 32))
+    // blocks up to 32^3 launch one workgroup of at most N^2 threads per block:
+    // the grid's thread count must stay below 2^32
+    if (nb >= MAX_BLOCKS || (N <= 32 && nb * N * N >= (1ull << 32)))
         return CZ_ERR_SHAPE;
     *nblocks = nb;
     return CZ_OK;
@@ -159,6 +161,23 @@ int take_status(cz_ctx *ctx, hipStream_t st)
     return rc;
 }
 
+// Scratch for the N = 64 kernels: one N^3 slot per workgroup of the grid.
+int ensure_scratch(cz_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->scratch_bytes)
+        return CZ_OK;
+    void *fresh = nullptr;
+    if (hipMalloc(&fresh, bytes) != hipSuccess)
+        return CZ_ERR_HIP;
+    if (ctx->scratch) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->scratch);
+    }
+    ctx->scratch = fresh;
+    ctx->scratch_bytes = bytes;
+    return CZ_OK;
+}
+
 int grid_for(cz_ctx *ctx, const czk::KernelKey &key, bool inverse, uint64_t nblocks)
 {
     int per_cu = czk::occupancy(key, inverse);
@@ -211,6 +230,8 @@ void cz_destroy(cz_ctx *ctx)
         (void)hipFree(ctx->work);
     if (ctx->pinned)
         (void)hipHostFree(ctx->pinned);
+    if (ctx->scratch)
+        (void)hipFree(ctx->scratch);
     delete ctx;
 }
 
@@ -282,8 +303,14 @@ int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_ou
         fa.eps_f = (float)p->epsilon;  // round to nearest, then up if it fell below
         if ((double)fa.eps_f < p->epsilon)
             fa.eps_f = std::nextafter(fa.eps_f, INFINITY);
-        // one workgroup per block (the forward kernel is not persistent)
-        if (czk::launch_fwd(key, fa, (int)nb, st) != hipSuccess)
+        int grid = (int)nb;  // one workgroup per block up to 32^3
+        if (p->block == 64) {  // persistent, one scratch slot per workgroup
+            grid = grid_for(ctx, key, false, nb);
+            if ((rc = ensure_scratch(ctx, (size_t)grid * 64 * 64 * 64 * p->elem_bytes)) != CZ_OK)
+                return rc;
+            fa.scratch = ctx->scratch;
+        }
+        if (czk::launch_fwd(key, fa, grid, st) != hipSuccess)
             return CZ_ERR_HIP;
     }
     if (d_out_bytes &&
@@ -378,7 +405,13 @@ int cz_decompress(cz_ctx *ctx, const cz_params *expected, const void *d_in, size
         ia.nblocks = nb;
         ia.p0 = p0;
         ia.payload = total - p0;
-        if (czk::launch_inv(key, ia, grid_for(ctx, key, true, nb), st) != hipSuccess)
+        const int grid = grid_for(ctx, key, true, nb);
+        if (p.block == 64) {
+            if ((rc = ensure_scratch(ctx, (size_t)grid * 64 * 64 * 64 * p.elem_bytes)) != CZ_OK)
+                return rc;
+            ia.scratch = ctx->scratch;
+        }
+        if (czk::launch_inv(key, ia, grid, st) != hipSuccess)
             return CZ_ERR_HIP;
     }
     if (sync) {

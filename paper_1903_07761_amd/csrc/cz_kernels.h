@@ -9,6 +9,9 @@
 
 namespace czk {
 
+// Threads per workgroup of the scratch-staged (N = 64) kernels.
+constexpr int SCRATCH_THREADS = 512;
+
 // Status bits latched by the kernels in CzWork::status.
 enum : uint32_t { STATUS_NONFINITE = 1u, STATUS_FORMAT = 2u, STATUS_TIMEOUT = 4u };
 
@@ -37,6 +40,7 @@ struct FwdArgs {
     uint64_t p0;         // payload start
     double eps;
     float eps_f;         // smallest float >= eps (the same test for float data)
+    void *scratch;       // N = 64: one N^3 slot of T per workgroup of the grid
 };
 
 struct InvArgs {
@@ -47,6 +51,7 @@ struct InvArgs {
     uint64_t nblocks;
     uint64_t p0;
     uint64_t payload;    // payload bytes from the header
+    void *scratch;       // N = 64: one N^3 slot of T per workgroup of the grid
 };
 
 struct PrepArgs {

@@ -683,6 +683,272 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
     }
 }
 
+// ------------------------------------------------- scratch-staged blocks
+// Blocks too large for a CU (N = 64: 1 MiB float, 2 MiB double) are
+// transformed in a per-workgroup scratch slot in global memory (L2/MALL
+// resident), one line per thread per pass, with full workgroup barriers
+// between passes (those must order global memory).  The arithmetic is the
+// same line code as the on-chip kernels; only the staging differs.
+
+template <int NT>
+__device__ __forceinline__ void gbarrier() { __syncthreads(); }
+
+// One axis pass (fwd or inv) over every line of [0,n)^3 of the N^3 block at
+// S (q = x + N (y + N z)); lanes run along x for y- and z-lines.
+template <typename T, int S, int N, int n, int AXIS, bool INV, int NT>
+__device__ __forceinline__ void scratch_pass(T *blk)
+{
+    constexpr int PY = N, PZ = N * N;
+    for (int l = threadIdx.x; l < n * n; l += NT) {
+        const int i = l % n, j = l / n;
+        int base, stride;
+        if constexpr (AXIS == 0) {
+            base = i * PY + j * PZ;
+            stride = 1;
+        } else if constexpr (AXIS == 1) {
+            base = i + j * PZ;
+            stride = PY;
+        } else {
+            base = i + j * PY;
+            stride = PZ;
+        }
+        T v[n];
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            v[k] = blk[base + k * stride];
+        if constexpr (INV)
+            line_inv<T, S, n>(v);
+        else
+            line_fwd<T, S, n>(v);
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            blk[base + k * stride] = v[k];
+    }
+}
+
+template <typename T, int S, int N, int n, int NT>
+__device__ __forceinline__ void scratch_levels_fwd(T *blk)
+{
+    scratch_pass<T, S, N, n, 0, false, NT>(blk);
+    gbarrier<NT>();
+    scratch_pass<T, S, N, n, 1, false, NT>(blk);
+    gbarrier<NT>();
+    scratch_pass<T, S, N, n, 2, false, NT>(blk);
+    gbarrier<NT>();
+    if constexpr (n / 2 >= 8)
+        scratch_levels_fwd<T, S, N, n / 2, NT>(blk);
+}
+
+template <typename T, int S, int N, int n, int NT>
+__device__ __forceinline__ void scratch_levels_inv(T *blk)
+{
+    if constexpr (n / 2 >= 8)
+        scratch_levels_inv<T, S, N, n / 2, NT>(blk);
+    scratch_pass<T, S, N, n, 2, true, NT>(blk);
+    gbarrier<NT>();
+    scratch_pass<T, S, N, n, 1, true, NT>(blk);
+    gbarrier<NT>();
+    scratch_pass<T, S, N, n, 0, true, NT>(blk);
+    gbarrier<NT>();
+}
+
+// Workgroup-wide exclusive scan of W word counts (W a multiple of NT): thread
+// t owns words [t K, t K + K).  Returns the total; s_pre receives prefixes.
+template <int NT, int W>
+__device__ __forceinline__ uint32_t scan_words(const uint64_t *s_words, uint32_t *s_pre, uint32_t *s_w)
+{
+    constexpr int K = W / NT;
+    static_assert(W % NT == 0, "words per thread must be whole");
+    uint32_t local[K];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        local[k] = (uint32_t)__popcll(s_words[threadIdx.x * K + k]);
+        sum += local[k];
+    }
+    const uint32_t pre = block_exclusive_scan<NT>(sum, s_w);
+    uint32_t run = pre;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        s_pre[threadIdx.x * K + k] = run;
+        run += local[k];
+    }
+    return s_w[NT / 64];
+}
+
+template <typename T, int N, int S>
+__global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(FwdArgs a)
+{
+    constexpr int NT = SCRATCH_THREADS;
+    constexpr int WORDS = N * N * N / 64;
+    constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
+    constexpr int WAVES = NT / 64;
+    __shared__ uint64_t s_words[WORDS];
+    __shared__ uint32_t s_pre[WORDS];
+    __shared__ uint32_t s_scan[WAVES + 1];
+    __shared__ uint64_t s_block;
+    __shared__ uint64_t s_off;
+    __shared__ uint32_t s_bad;
+
+    const int tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const int wave = tid / 64;
+    const size_t plane = (size_t)a.nx * a.ny;
+    T *blkS = static_cast<T *>(a.scratch) + (size_t)blockIdx.x * N * N * N;
+
+    while (true) {
+        if (tid == 0) {
+            s_block = atomicAdd(&a.work->ticket, 1u);
+            s_bad = 0;
+        }
+        gbarrier<NT>();
+        const uint64_t b = s_block;
+        if (b >= a.nblocks)
+            break;
+        const uint32_t bx = (uint32_t)(b % a.nbx);
+        const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
+        const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
+        const T *src = static_cast<const T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+        bool bad = false;
+        for (int q = tid; q < N * N * N; q += NT) {
+            const int x = q % N, y = (q / N) % N, z = q / (N * N);
+            const T v = src[(size_t)z * plane + (size_t)y * a.nx + x];
+            bad |= !finite(v);
+            blkS[q] = v;
+        }
+        gbarrier<NT>();
+        scratch_levels_fwd<T, S, N, N, NT>(blkS);
+
+        // decimation: wavefront w takes words w, w + WAVES, ...
+        for (int w = wave; w < WORDS; w += WAVES) {
+            const int q = w * 64 + (int)lane;
+            const int x = q % N, y = (q / N) % N, z = q / (N * N);
+            const T v = blkS[q];
+            bad |= !finite(v);
+            const bool keep = (x < 4 && y < 4 && z < 4) || keep_test<T>(v, a);
+            const uint64_t m = __ballot(keep);
+            if (lane == 0)
+                s_words[w] = m;
+        }
+        if (bad)
+            s_bad = 1;
+        gbarrier<NT>();
+        if (tid == 0 && s_bad)
+            atomicOr(&a.work->status, STATUS_NONFINITE);
+        const uint32_t nnz = scan_words<NT, WORDS>(s_words, s_pre, s_scan);
+        const uint64_t used = 8ull + MASK_BYTES + (uint64_t)nnz * sizeof(T);
+        const uint64_t rbytes = (used + 15ull) & ~15ull;
+        if (tid == 0)
+            s_off = lookback(a.flags, b, rbytes, &a.work->status);
+        gbarrier<NT>();
+        const uint64_t off = s_off;
+        uint8_t *rec = a.out + a.p0 + off;
+        if (tid == 0) {
+            reinterpret_cast<uint32_t *>(rec)[0] = nnz;
+            reinterpret_cast<uint32_t *>(rec)[1] = 0u;
+            a.offsets[b + 1] = off + rbytes;
+            for (uint64_t p = used; p < rbytes; p += 4)
+                *reinterpret_cast<uint32_t *>(rec + p) = 0u;
+            if (b + 1 == a.nblocks) {
+                *reinterpret_cast<uint64_t *>(a.out + 56) = off + rbytes;
+                a.work->total = a.p0 + off + rbytes;
+            }
+        }
+        uint64_t *mask = reinterpret_cast<uint64_t *>(rec + 8);
+        for (int w = tid; w < WORDS; w += NT)
+            mask[w] = s_words[w];
+        const rsrc_t vr = make_rsrc(rec + 8 + MASK_BYTES, nnz * (uint32_t)sizeof(T));
+        for (int w = wave; w < WORDS; w += WAVES) {
+            const uint64_t m = s_words[w];
+            if ((m >> lane) & 1ull)
+                buf_store(blkS[w * 64 + (int)lane], vr, (s_pre[w] + mbcnt(m)) * (uint32_t)sizeof(T));
+        }
+        gbarrier<NT>();
+    }
+}
+
+template <typename T, int N, int S>
+__global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(InvArgs a)
+{
+    constexpr int NT = SCRATCH_THREADS;
+    constexpr int WORDS = N * N * N / 64;
+    constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
+    constexpr int WAVES = NT / 64;
+    __shared__ uint64_t s_words[WORDS];
+    __shared__ uint32_t s_pre[WORDS];
+    __shared__ uint32_t s_scan[WAVES + 1];
+    __shared__ uint64_t s_block;
+    __shared__ uint32_t s_ok;
+
+    const int tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const int wave = tid / 64;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const uint64_t *offs = reinterpret_cast<const uint64_t *>(a.in + 64);
+    T *blkS = static_cast<T *>(a.scratch) + (size_t)blockIdx.x * N * N * N;
+
+    while (true) {
+        if (tid == 0) {
+            const uint64_t b = atomicAdd(&a.work->ticket, 1u);
+            s_block = b;
+            uint32_t ok = 0;
+            if (b < a.nblocks) {
+                const uint64_t o0 = offs[b], o1 = offs[b + 1];
+                ok = o1 >= o0 && o1 <= a.payload && o1 - o0 >= 8ull + MASK_BYTES;
+                if (ok) {
+                    const uint32_t nnz = *reinterpret_cast<const uint32_t *>(a.in + a.p0 + o0);
+                    const uint64_t used = 8ull + MASK_BYTES + (uint64_t)nnz * sizeof(T);
+                    ok = nnz <= (uint32_t)(N * N * N) && ((used + 15ull) & ~15ull) == o1 - o0;
+                }
+                if (!ok)
+                    atomicOr(&a.work->status, STATUS_FORMAT);
+            }
+            s_ok = ok;
+        }
+        gbarrier<NT>();
+        const uint64_t b = s_block;
+        if (b >= a.nblocks)
+            break;
+        if (!s_ok) {
+            gbarrier<NT>();
+            continue;
+        }
+        const uint8_t *rec = a.in + a.p0 + offs[b];
+        const uint32_t nnz = *reinterpret_cast<const uint32_t *>(rec);
+        const uint64_t *mask = reinterpret_cast<const uint64_t *>(rec + 8);
+        const rsrc_t vr = make_rsrc(rec + 8 + MASK_BYTES, nnz * (uint32_t)sizeof(T));
+        for (int w = tid; w < WORDS; w += NT)
+            s_words[w] = mask[w];
+        gbarrier<NT>();
+        const uint32_t total = scan_words<NT, WORDS>(s_words, s_pre, s_scan);
+        gbarrier<NT>();
+        if (total != nnz) {
+            if (tid == 0)
+                atomicOr(&a.work->status, STATUS_FORMAT);
+            gbarrier<NT>();
+            continue;
+        }
+        for (int w = wave; w < WORDS; w += WAVES) {
+            const uint64_t m = s_words[w];
+            T v = T(0);
+            if ((m >> lane) & 1ull)
+                v = buf_load<T>(vr, (s_pre[w] + mbcnt(m)) * (uint32_t)sizeof(T));
+            blkS[w * 64 + (int)lane] = v;
+        }
+        gbarrier<NT>();
+        scratch_levels_inv<T, S, N, N, NT>(blkS);
+        const uint32_t bx = (uint32_t)(b % a.nbx);
+        const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
+        const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
+        T *dst = static_cast<T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+        for (int q = tid; q < N * N * N; q += NT) {
+            const int x = q % N, y = (q / N) % N, z = q / (N * N);
+            dst[(size_t)z * plane + (size_t)y * a.nx + x] = blkS[q];
+        }
+        gbarrier<NT>();
+    }
+}
+
 // ------------------------------------------------------------- bookkeeping
 
 // Reset the ticket and status, clear the look-back flags, write the header
@@ -763,6 +1029,8 @@ static int occupancy_t(bool inverse)
 
 int threads_per_block(const KernelKey &key)
 {
+    if (key.block == 64)
+        return SCRATCH_THREADS;
     const bool big = key.elem_bytes == 8 && key.block >= 32;
     return (int)(key.block * key.block) / (big ? 2 : 1);
 }
@@ -789,8 +1057,32 @@ int threads_per_block(const KernelKey &key)
         }                                                                                                    \
     }
 
+template <typename T, int S>
+static hipError_t launch_fwd_scratch_t(const FwdArgs &a, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((fwd_scratch_kernel<T, 64, S>), dim3(grid), dim3(SCRATCH_THREADS), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int S>
+static hipError_t launch_inv_scratch_t(const InvArgs &a, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((inv_scratch_kernel<T, 64, S>), dim3(grid), dim3(SCRATCH_THREADS), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_fwd(const KernelKey &key, const FwdArgs &a, int grid, hipStream_t st)
 {
+    if (key.block == 64) {
+        const bool f = key.elem_bytes == 4;
+        switch (key.scheme) {
+        case W4: return f ? launch_fwd_scratch_t<float, W4>(a, grid, st) : launch_fwd_scratch_t<double, W4>(a, grid, st);
+        case W4LI:
+            return f ? launch_fwd_scratch_t<float, W4LI>(a, grid, st) : launch_fwd_scratch_t<double, W4LI>(a, grid, st);
+        default:
+            return f ? launch_fwd_scratch_t<float, W3AI>(a, grid, st) : launch_fwd_scratch_t<double, W3AI>(a, grid, st);
+        }
+    }
     if (key.elem_bytes == 4) {
         CZ_DISPATCH(float, launch_fwd_t, (a, grid, st))
     } else {
@@ -800,6 +1092,16 @@ hipError_t launch_fwd(const KernelKey &key, const FwdArgs &a, int grid, hipStrea
 
 hipError_t launch_inv(const KernelKey &key, const InvArgs &a, int grid, hipStream_t st)
 {
+    if (key.block == 64) {
+        const bool f = key.elem_bytes == 4;
+        switch (key.scheme) {
+        case W4: return f ? launch_inv_scratch_t<float, W4>(a, grid, st) : launch_inv_scratch_t<double, W4>(a, grid, st);
+        case W4LI:
+            return f ? launch_inv_scratch_t<float, W4LI>(a, grid, st) : launch_inv_scratch_t<double, W4LI>(a, grid, st);
+        default:
+            return f ? launch_inv_scratch_t<float, W3AI>(a, grid, st) : launch_inv_scratch_t<double, W3AI>(a, grid, st);
+        }
+    }
     if (key.elem_bytes == 4) {
         CZ_DISPATCH(float, launch_inv_t, (a, grid, st))
     } else {
@@ -809,6 +1111,8 @@ hipError_t launch_inv(const KernelKey &key, const InvArgs &a, int grid, hipStrea
 
 int occupancy(const KernelKey &key, bool inverse)
 {
+    if (key.block == 64)
+        return 1;  // one scratch slot per workgroup, one workgroup per CU
     if (key.elem_bytes == 4) {
         CZ_DISPATCH(float, occupancy_t, (inverse))
     } else {

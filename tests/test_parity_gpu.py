@@ -62,6 +62,7 @@ CASES = [
     (16, (32, 48, 16)),
     (32, (32, 96, 64)),
     (32, (64, 32, 32)),
+    (64, (64, 64, 128)),  # scratch-staged path
 ]
 
 
