@@ -137,6 +137,65 @@ int cz_read_header(const void *h_hdr, size_t n, cz_params *out, uint64_t *nblock
 
 const char *cz_strerror(int code);
 
+/* ------------------------------------------------------------ kernel tuning
+ *
+ * Each (N, precision) has one or more register/LDS tilings of the same
+ * transform (how many z-columns a thread owns, how many planes stay in LDS);
+ * every variant yields byte-identical streams and fields.  cz_variant_count
+ * returns how many exist (0 for an unsupported pair); cz_set_variant selects
+ * one for later calls of ctx on (block, elem_bytes, scheme) (default 0).
+ * Returns CZ_ERR_ARG for an unknown variant. */
+int cz_variant_count(uint32_t block, uint32_t elem_bytes);
+int cz_set_variant(cz_ctx *ctx, uint32_t block, uint32_t elem_bytes, uint32_t scheme, int variant);
+
+/* ------------------------------------------------------------------ batches
+ *
+ * Several independent fields (Sec. 2.2: each quantity of a time step is
+ * compressed on its own) in one call.  Fields are grouped by (N, precision,
+ * scheme, variant); each group runs as one launch that pulls blocks of all its
+ * fields from a device work queue, and the groups run concurrently on streams
+ * forked from `stream` and joined back to it.  Every output is byte-identical
+ * to the single-field call with the same parameters.
+ *
+ * cz_compress_batch: field i (params ps[i], device d_fields[i]) -> stream at
+ * d_outs[i] of capacity caps[i] (>= cz_compress_bound(&ps[i]), else
+ * CZ_ERR_CAPACITY and, when h_out_bytes != NULL, the bound in h_out_bytes[i]).
+ * Sizes go to the device array d_out_bytes[n] (if non-null) and, when
+ * h_out_bytes != NULL, to h_out_bytes[n] after waiting (synchronous; device
+ * errors are returned and cleared as for cz_compress).  Otherwise the call is
+ * asynchronous and errors are read with cz_get_status.
+ *
+ * cz_decompress_batch: stream i (d_ins[i], in_bytes[i] = its total size, its
+ * header matching ps[i]) -> field d_fields[i] of capacity caps[i] bytes.
+ * Asynchronous; device errors (CZ_ERR_FORMAT, ...) via cz_get_status.
+ *
+ * At most 24 groups per call; the host arrays are read before the call
+ * returns.  The pointer arrays are host memory, the pointers in them device
+ * memory. */
+int cz_compress_batch(cz_ctx *ctx, int n, const cz_params *ps, const void *const *d_fields, void *const *d_outs,
+                      const size_t *caps, uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream);
+int cz_decompress_batch(cz_ctx *ctx, int n, const cz_params *ps, const void *const *d_ins, const size_t *in_bytes,
+                        void *const *d_fields, const size_t *caps, void *stream);
+
+/* ------------------------------------------------------------ captured plans
+ *
+ * A plan fixes the parameters of a batch (op 0 = compress, 1 = decompress) and
+ * owns its workspace; its first run records the batch's launches into a HIP
+ * graph (descriptor upload, per-group kernels on forked streams, status fold,
+ * size readback) and every later run replays it with new buffers, so a
+ * repeated batch costs one graph launch.  cz_plan_run takes the same buffer
+ * arrays as the batch calls (src_bytes: stream sizes for op 1, ignored for
+ * op 0) and is asynchronous; cz_plan_result waits for `stream` and returns the
+ * run's error (cleared) and, for op 0, the stream sizes in h_out_bytes[n].
+ * A plan shares the status word of its context: runs of plans of one context
+ * must not overlap with each other or with the context's other calls. */
+typedef struct cz_plan cz_plan;
+int cz_plan_create(cz_ctx *ctx, int op, int n, const cz_params *ps, cz_plan **out);
+int cz_plan_run(cz_plan *plan, const void *const *srcs, const size_t *src_bytes, void *const *dsts,
+                const size_t *dst_caps, void *stream);
+int cz_plan_result(cz_plan *plan, void *stream, size_t *h_out_bytes);
+void cz_plan_destroy(cz_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,24 @@ def lib() -> ctypes.CDLL:
         L.cz_read_header.restype = i32
         L.cz_strerror.argtypes = [i32]
         L.cz_strerror.restype = ctypes.c_char_p
+        u32, PP = ctypes.c_uint32, ctypes.POINTER(vp)
+        PS = ctypes.POINTER(sz)
+        L.cz_variant_count.argtypes = [u32, u32]
+        L.cz_variant_count.restype = i32
+        L.cz_set_variant.argtypes = [vp, u32, u32, u32, i32]
+        L.cz_set_variant.restype = i32
+        L.cz_compress_batch.argtypes = [vp, i32, P, PP, PP, PS, vp, PS, vp]
+        L.cz_compress_batch.restype = i32
+        L.cz_decompress_batch.argtypes = [vp, i32, P, PP, PS, PP, PS, vp]
+        L.cz_decompress_batch.restype = i32
+        L.cz_plan_create.argtypes = [vp, i32, i32, P, PP]
+        L.cz_plan_create.restype = i32
+        L.cz_plan_run.argtypes = [vp, PP, PS, PP, PS, vp]
+        L.cz_plan_run.restype = i32
+        L.cz_plan_result.argtypes = [vp, vp, PS]
+        L.cz_plan_result.restype = i32
+        L.cz_plan_destroy.argtypes = [vp]
+        L.cz_plan_destroy.restype = None
         _lib = L
     return _lib
 
@@ -123,6 +141,85 @@ class Context:
 
     def get_status(self, stream: int = 0) -> int:
         return lib().cz_get_status(self.handle, stream)
+
+    def set_variant(self, block: int, elem_bytes: int, scheme, variant: int):
+        s = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        _check(lib().cz_set_variant(self.handle, block, elem_bytes, s, variant), "cz_set_variant")
+
+    def compress_batch(self, ps, d_fields, d_outs, caps, stream: int = 0, d_out_bytes: int | None = None,
+                       sync: bool = True):
+        """cz_compress_batch; returns the stream sizes when sync."""
+        n = len(ps)
+        sizes = _sizes(n)
+        rc = lib().cz_compress_batch(self.handle, n, _params_array(ps), _ptrs(d_fields), _ptrs(d_outs),
+                                     _sizes(n, caps), d_out_bytes, sizes if sync else None, stream)
+        if rc != OK:
+            raise CzError(rc, "cz_compress_batch", f"(required {list(sizes)} bytes)" if rc == ERR_CAPACITY else "")
+        return list(sizes) if sync else None
+
+    def decompress_batch(self, ps, d_ins, in_bytes, d_fields, caps, stream: int = 0):
+        n = len(ps)
+        _check(lib().cz_decompress_batch(self.handle, n, _params_array(ps), _ptrs(d_ins), _sizes(n, in_bytes),
+                                         _ptrs(d_fields), _sizes(n, caps), stream), "cz_decompress_batch")
+
+
+def _params_array(ps):
+    arr = (cz_params * max(len(ps), 1))()
+    for i, p in enumerate(ps):
+        arr[i] = p
+    return arr
+
+
+def _ptrs(vals):
+    arr = (ctypes.c_void_p * max(len(vals), 1))()
+    for i, v in enumerate(vals):
+        arr[i] = v
+    return arr
+
+
+def _sizes(n, vals=None):
+    arr = (ctypes.c_size_t * max(n, 1))()
+    if vals is not None:
+        for i, v in enumerate(vals):
+            arr[i] = int(v)
+    return arr
+
+
+def variant_count(block: int, elem_bytes: int) -> int:
+    return int(lib().cz_variant_count(block, elem_bytes))
+
+
+class Plan:
+    """A captured batch (op "compress" or "decompress") with fixed parameters."""
+
+    def __init__(self, ctx: Context, op: str, ps):
+        self.ctx = ctx
+        self.n = len(ps)
+        self.forward = op == "compress"
+        h = ctypes.c_void_p()
+        _check(lib().cz_plan_create(ctx.handle, 0 if self.forward else 1, self.n, _params_array(ps),
+                                    ctypes.byref(h)), "cz_plan_create")
+        self.handle = h
+
+    def run(self, srcs, dsts, caps, src_bytes=None, stream: int = 0):
+        _check(lib().cz_plan_run(self.handle, _ptrs(srcs), _sizes(self.n, src_bytes) if src_bytes is not None
+                                 else None, _ptrs(dsts), _sizes(self.n, caps), stream), "cz_plan_run")
+
+    def result(self, stream: int = 0):
+        sizes = _sizes(self.n)
+        _check(lib().cz_plan_result(self.handle, stream, sizes), "cz_plan_result")
+        return list(sizes) if self.forward else None
+
+    def close(self):
+        if self.handle:
+            lib().cz_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def compress_bound(p: cz_params) -> int:

@@ -65,3 +65,34 @@ class Codec:
 
     def status(self) -> int:
         return self.ctx.get_status(_stream_handle(self.device))
+
+    def set_variant(self, block: int, dtype, scheme, variant: int):
+        self.ctx.set_variant(block, _ELEM[dtype], scheme, variant)
+
+    def batch_params(self, fields, blocks, schemes, epsilons):
+        return [self.params(f, b, s, e) for f, b, s, e in zip(fields, blocks, schemes, epsilons)]
+
+    def compress_batch(self, fields, blocks, schemes, epsilons, outs=None, sync: bool = True,
+                       out_bytes: torch.Tensor | None = None):
+        """Compress several contiguous [nz, ny, nx] device fields in one call.
+        Returns (stream buffers, sizes or None)."""
+        for f in fields:
+            assert f.is_cuda and f.is_contiguous() and f.dim() == 3
+        ps = self.batch_params(fields, blocks, schemes, epsilons)
+        if outs is None:
+            outs = [torch.empty(_cz.compress_bound(p), dtype=torch.uint8, device=self.device) for p in ps]
+        sizes = self.ctx.compress_batch(ps, [f.data_ptr() for f in fields], [o.data_ptr() for o in outs],
+                                        [o.numel() for o in outs], _stream_handle(self.device),
+                                        out_bytes.data_ptr() if out_bytes is not None else None, sync)
+        return outs, sizes
+
+    def decompress_batch(self, bufs, nbytes, ps, outs=None):
+        """Rebuild several fields; ps[i] are the parameters the stream was made with."""
+        if outs is None:
+            outs = [torch.empty((p.nz, p.ny, p.nx), dtype=_DTYPE[p.elem_bytes], device=self.device) for p in ps]
+        self.ctx.decompress_batch(ps, [b.data_ptr() for b in bufs], list(nbytes), [o.data_ptr() for o in outs],
+                                  [o.numel() * o.element_size() for o in outs], _stream_handle(self.device))
+        return outs
+
+    def plan(self, op: str, ps) -> _cz.Plan:
+        return _cz.Plan(self.ctx, op, ps)

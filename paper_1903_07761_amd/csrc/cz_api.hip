@@ -1,35 +1,178 @@
 // Host side of the C ABI declared in include/cz.h: parameter validation,
-// stream layout arithmetic, workspace ownership and kernel launches.
+// stream layout arithmetic, workspace ownership, work queues and launches.
 //
 // The problem statement (arXiv 1903.07761, Sec. 2.1-2.3): a grid of equal
 // cubic blocks of power-of-two edge, one scalar quantity at a time, a wavelet
 // scheme, a precision and a decimation threshold.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <new>
+#include <tuple>
+#include <vector>
 
 #include "../../include/cz.h"
 #include "cz_kernels.h"
-
-struct cz_ctx {
-    int device = 0;
-    int num_cu = 0;
-    czk::CzWork *work = nullptr;  // device: ticket, status, total
-    uint64_t *flags = nullptr;    // device: look-back flags
-    uint64_t cap_blocks = 0;
-    czk::CzWork *pinned = nullptr;  // host-pinned mirror of *work for sync reads
-    void *scratch = nullptr;        // N = 64 blocks: one slot per resident workgroup
-    size_t scratch_bytes = 0;
-};
 
 namespace {
 
 constexpr uint32_t MAGIC = 0x31425A43u;  // "CZB1" little-endian
 constexpr uint64_t MAX_BLOCKS = 1ull << 31;
 constexpr uint64_t HDR = 64;
+constexpr int MAX_CLASSES = 24;  // 4 block sizes x 2 precisions x 3 schemes
+
+// Device memory that grows on demand (freed with its owner).
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t want)
+    {
+        if (want <= bytes)
+            return CZ_OK;
+        void *fresh = nullptr;
+        if (hipMalloc(&fresh, want) != hipSuccess)
+            return CZ_ERR_HIP;
+        if (ptr) {
+            (void)hipDeviceSynchronize();  // earlier work may still use the old buffer
+            (void)hipFree(ptr);
+        }
+        ptr = fresh;
+        bytes = want;
+        return CZ_OK;
+    }
+    void release()
+    {
+        if (ptr)
+            (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+};
+
+// Workspace of a batch: the device descriptor table and its pinned staging,
+// look-back flags, per-class (ticket, status) counters, stream sizes, 64^3
+// scratch, and the lanes the classes run on concurrently.
+struct BatchWork {
+    DevBuf desc, flags, counters, totals, scratch;
+    czk::FieldDesc *stage = nullptr;  // pinned, uploaded in stream order
+    uint64_t *totals_host = nullptr;  // pinned readback of stream sizes
+    size_t cap = 0;                   // fields the pinned buffers hold
+    hipEvent_t staged = nullptr;      // the staging may be rewritten once this fired
+    hipStream_t lanes[MAX_CLASSES] = {};
+    hipEvent_t fork = nullptr, joins[MAX_CLASSES] = {};
+
+    int init()
+    {
+        if (hipEventCreateWithFlags(&staged, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(staged, nullptr) != hipSuccess)
+            return CZ_ERR_HIP;
+        return CZ_OK;
+    }
+    // Streams (default priority) and join events for the first n lanes.
+    int lanes_for(size_t n)
+    {
+        for (size_t i = 0; i < n && i < (size_t)MAX_CLASSES; ++i) {
+            if (!lanes[i] && hipStreamCreateWithFlags(&lanes[i], hipStreamNonBlocking) != hipSuccess)
+                return CZ_ERR_HIP;
+            if (!joins[i] && hipEventCreateWithFlags(&joins[i], hipEventDisableTiming) != hipSuccess)
+                return CZ_ERR_HIP;
+        }
+        return CZ_OK;
+    }
+    int pinned(size_t n)
+    {
+        if (n <= cap)
+            return CZ_OK;
+        if (staged)
+            (void)hipEventSynchronize(staged);
+        if (stage)
+            (void)hipHostFree(stage);
+        if (totals_host)
+            (void)hipHostFree(totals_host);
+        stage = nullptr;
+        totals_host = nullptr;
+        cap = 0;
+        if (hipHostMalloc(&stage, n * sizeof(czk::FieldDesc), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&totals_host, n * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+            return CZ_ERR_HIP;
+        cap = n;
+        return CZ_OK;
+    }
+    void release()
+    {
+        desc.release();
+        flags.release();
+        counters.release();
+        totals.release();
+        scratch.release();
+        if (stage)
+            (void)hipHostFree(stage);
+        if (totals_host)
+            (void)hipHostFree(totals_host);
+        if (staged)
+            (void)hipEventDestroy(staged);
+        if (fork)
+            (void)hipEventDestroy(fork);
+        for (int i = 0; i < MAX_CLASSES; ++i) {
+            if (lanes[i])
+                (void)hipStreamDestroy(lanes[i]);
+            if (joins[i])
+                (void)hipEventDestroy(joins[i]);
+        }
+    }
+};
+
+}  // namespace
+
+struct cz_ctx {
+    int device = 0;
+    int num_cu = 0;
+    czk::CzWork *work = nullptr;    // device: ticket, status, total of plain calls
+    czk::CzWork *pinned = nullptr;  // host-pinned mirror for synchronous reads
+    DevBuf flags;                   // plain calls: look-back flags
+    DevBuf scratch;                 // plain calls on 64^3 blocks: one slot per resident workgroup
+    uint8_t variant[4][2][3] = {};  // tuned kernel variant per (N, precision, scheme)
+    BatchWork batch;                // batch calls
+};
+
+namespace {
+
+// Class of a field: fields of one class share a kernel and one queue.
+using ClassKey = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>;
+
+struct Layout {
+    bool forward = true;
+    int n = 0;
+    std::vector<uint64_t> nblocks;      // per field
+    std::vector<int> order;             // field indices grouped by class
+    std::vector<czk::KernelKey> keys;   // per class
+    std::vector<uint32_t> first, count; // per class: its range in `order`
+    std::vector<uint64_t> tickets;      // per class
+    std::vector<int> grids;             // per class
+    std::vector<size_t> scratch_off;    // per class: its 64^3 slots
+    size_t scratch_bytes = 0;
+    std::vector<uint64_t> flag_base;    // per field (forward): offset into the flags
+    uint64_t flags_total = 0;
+};
+
+}  // namespace
+
+struct cz_plan {
+    cz_ctx *ctx = nullptr;
+    std::vector<cz_params> params;
+    Layout layout;
+    BatchWork work;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // the last run has finished with the staging
+};
+
+namespace {
 
 struct DeviceGuard {
     int prev = -1;
@@ -94,41 +237,58 @@ uint64_t record_bound(uint32_t N, uint32_t elem)
     return roundup16(8 + n3 / 8 + n3 * elem);
 }
 
-void build_header(const cz_params *p, uint64_t nblocks, uint32_t out[16])
+uint64_t bound_of(const cz_params &p, uint64_t nb) { return payload_start(nb) + nb * record_bound(p.block, p.elem_bytes); }
+
+void build_header(const cz_params &p, uint64_t nblocks, uint32_t out[16])
 {
     std::memset(out, 0, 64);
     out[0] = MAGIC;
     out[1] = 1;
-    out[2] = p->scheme;
-    out[3] = p->elem_bytes;
-    out[4] = p->block;
-    out[5] = (uint32_t)(ilog2(p->block) - 2);
-    out[6] = p->nx;
-    out[7] = p->ny;
-    out[8] = p->nz;
+    out[2] = p.scheme;
+    out[3] = p.elem_bytes;
+    out[4] = p.block;
+    out[5] = (uint32_t)(ilog2(p.block) - 2);
+    out[6] = p.nx;
+    out[7] = p.ny;
+    out[8] = p.nz;
     out[9] = 0;
-    std::memcpy(&out[10], &p->epsilon, 8);
+    std::memcpy(&out[10], &p.epsilon, 8);
     std::memcpy(&out[12], &nblocks, 8);
     // out[14..15] payload bytes: written by the last block
 }
 
-int ensure_capacity(cz_ctx *ctx, uint64_t nblocks)
+float eps_float(double eps)
 {
-    if (nblocks <= ctx->cap_blocks)
-        return CZ_OK;
-    uint64_t want = ctx->cap_blocks ? ctx->cap_blocks : 4096;
-    while (want < nblocks)
-        want *= 2;
-    uint64_t *fresh = nullptr;
-    if (hipMalloc(&fresh, want * sizeof(uint64_t)) != hipSuccess)
-        return CZ_ERR_HIP;
-    if (ctx->flags) {
-        (void)hipDeviceSynchronize();  // previous calls may still use the old flags
-        (void)hipFree(ctx->flags);
-    }
-    ctx->flags = fresh;
-    ctx->cap_blocks = want;
-    return CZ_OK;
+    float f = (float)eps;  // round to nearest, then up if it fell below
+    if ((double)f < eps)
+        f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+int block_index(uint32_t N) { return N == 8 ? 0 : N == 16 ? 1 : N == 32 ? 2 : 3; }
+
+czk::KernelKey key_of(const cz_ctx *ctx, const cz_params &p)
+{
+    czk::KernelKey k{p.block, p.scheme, p.elem_bytes, 0};
+    k.variant = ctx->variant[block_index(p.block)][p.elem_bytes == 8][p.scheme];
+    return k;
+}
+
+// Descriptor of one field (pointers and ticket base filled by the caller).
+czk::FieldDesc describe(const cz_params &p, uint64_t nb, bool forward)
+{
+    czk::FieldDesc d{};
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.nbx = p.nx / p.block;
+    d.nby = p.ny / p.block;
+    d.nblocks = nb;
+    d.p0 = payload_start(nb);
+    d.eps = p.epsilon;
+    d.eps_f = eps_float(p.epsilon);
+    if (forward)
+        build_header(p, nb, d.header);
+    return d;
 }
 
 int status_to_error(uint32_t st)
@@ -152,41 +312,186 @@ int read_work(cz_ctx *ctx, hipStream_t st)
     return CZ_OK;
 }
 
+czk::Queue work_queue(cz_ctx *ctx)
+{
+    czk::Queue q{};
+    q.nfields = 1;
+    q.ticket = &ctx->work->ticket;
+    q.status = &ctx->work->status;
+    return q;
+}
+
 // Synchronous calls report their device-side error and consume it.
 int take_status(cz_ctx *ctx, hipStream_t st)
 {
     const int rc = status_to_error(ctx->pinned->status);
-    if (ctx->pinned->status != 0 && czk::launch_prep_inv(ctx->work, st) != hipSuccess)
+    if (ctx->pinned->status != 0 && czk::launch_prep(work_queue(ctx), false, st) != hipSuccess)
         return CZ_ERR_HIP;
     return rc;
 }
 
-// Scratch for the N = 64 kernels: one N^3 slot per workgroup of the grid.
-int ensure_scratch(cz_ctx *ctx, size_t bytes)
+// Workgroups of a launch over `tickets` blocks: one per block for the
+// on-chip forward kernel, else enough persistent workgroups to fill the chip.
+int grid_for(const cz_ctx *ctx, const czk::KernelKey &key, bool inverse, uint64_t tickets)
 {
-    if (bytes <= ctx->scratch_bytes)
-        return CZ_OK;
-    void *fresh = nullptr;
-    if (hipMalloc(&fresh, bytes) != hipSuccess)
-        return CZ_ERR_HIP;
-    if (ctx->scratch) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->scratch);
-    }
-    ctx->scratch = fresh;
-    ctx->scratch_bytes = bytes;
-    return CZ_OK;
-}
-
-int grid_for(cz_ctx *ctx, const czk::KernelKey &key, bool inverse, uint64_t nblocks)
-{
+    if (!inverse && czk::fwd_one_block_per_workgroup(key))
+        return (int)std::max<uint64_t>(tickets, 1);
     int per_cu = czk::occupancy(key, inverse);
     if (per_cu < 1)
         per_cu = 1;
     uint64_t g = (uint64_t)per_cu * (uint64_t)ctx->num_cu;
-    if (g > nblocks)
-        g = nblocks;
+    if (g > tickets)
+        g = tickets;
     return (int)(g ? g : 1);
+}
+
+size_t scratch_need(const czk::KernelKey &key, int grid)
+{
+    return key.block == 64 ? (size_t)grid * 64 * 64 * 64 * key.elem_bytes : 0;
+}
+
+// Group the fields of a batch into classes (block size, precision, scheme,
+// variant), each with a ticket range, a grid and its own 64^3 scratch slots.
+int layout_batch(const cz_ctx *ctx, bool forward, int n, const cz_params *ps, Layout *L)
+{
+    std::map<ClassKey, std::vector<int>> by;
+    L->forward = forward;
+    L->n = n;
+    L->nblocks.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        int rc = check_params(&ps[i], &L->nblocks[i]);
+        if (rc != CZ_OK)
+            return rc;
+        const czk::KernelKey k = key_of(ctx, ps[i]);
+        by[ClassKey(k.block, k.elem_bytes, k.scheme, k.variant)].push_back(i);
+    }
+    if ((int)by.size() > MAX_CLASSES)
+        return CZ_ERR_ARG;
+    L->flag_base.assign(n, 0);
+    for (auto &kv : by) {
+        const czk::KernelKey key{std::get<0>(kv.first), std::get<2>(kv.first), std::get<1>(kv.first),
+                                 std::get<3>(kv.first)};
+        L->keys.push_back(key);
+        L->first.push_back((uint32_t)L->order.size());
+        L->count.push_back((uint32_t)kv.second.size());
+        uint64_t t = 0;
+        for (int i : kv.second) {
+            L->order.push_back(i);
+            L->flag_base[i] = L->flags_total;
+            L->flags_total += std::max<uint64_t>(L->nblocks[i], 1);
+            t += L->nblocks[i];
+        }
+        L->tickets.push_back(t);
+        const int g = grid_for(ctx, key, !forward, t);
+        L->grids.push_back(g);
+        L->scratch_off.push_back(L->scratch_bytes);
+        L->scratch_bytes += scratch_need(key, g);
+    }
+    return CZ_OK;
+}
+
+int size_work(BatchWork &w, const Layout &L)
+{
+    int rc;
+    if ((rc = w.desc.ensure(std::max(L.n, 1) * sizeof(czk::FieldDesc))) != CZ_OK ||
+        (rc = w.flags.ensure(std::max<uint64_t>(L.flags_total, 1) * sizeof(uint64_t))) != CZ_OK ||
+        (rc = w.counters.ensure(2 * MAX_CLASSES * sizeof(uint32_t))) != CZ_OK ||
+        (rc = w.totals.ensure(std::max(L.n, 1) * sizeof(uint64_t))) != CZ_OK ||
+        (rc = w.scratch.ensure(std::max<size_t>(L.scratch_bytes, 1))) != CZ_OK || (rc = w.pinned(L.n)) != CZ_OK ||
+        (rc = w.lanes_for(L.keys.size())) != CZ_OK)
+        return rc;
+    return CZ_OK;
+}
+
+// Fill the pinned descriptor table for buffers srcs -> dsts (class order).
+void stage_batch(BatchWork &w, const Layout &L, const cz_params *ps, const void *const *srcs,
+                 const size_t *src_bytes, void *const *dsts)
+{
+    uint64_t *flags = static_cast<uint64_t *>(w.flags.ptr);
+    uint64_t *totals = static_cast<uint64_t *>(w.totals.ptr);
+    for (size_t c = 0; c < L.keys.size(); ++c) {
+        uint64_t t = 0;
+        for (uint32_t k = 0; k < L.count[c]; ++k) {
+            const int i = L.order[L.first[c] + k];
+            czk::FieldDesc d = describe(ps[i], L.nblocks[i], L.forward);
+            d.src = srcs[i];
+            d.dst = dsts[i];
+            d.first = t;
+            t += L.nblocks[i];
+            if (L.forward) {
+                d.flags = flags + L.flag_base[i];
+                d.total = totals + i;
+            } else {
+                d.payload = src_bytes[i] - d.p0;
+            }
+            w.stage[L.first[c] + k] = d;
+        }
+    }
+}
+
+// Enqueue a staged batch on st: upload the descriptors, then every class on
+// its own lane (forked from st, joined back), then fold the class status
+// words into *status and copy the stream sizes to pinned memory.
+int enqueue_batch(BatchWork &w, const Layout &L, uint32_t *status, hipStream_t st)
+{
+    czk::FieldDesc *desc = static_cast<czk::FieldDesc *>(w.desc.ptr);
+    uint32_t *counters = static_cast<uint32_t *>(w.counters.ptr);
+    if (hipMemcpyAsync(desc, w.stage, L.n * sizeof(czk::FieldDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(w.fork, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    for (size_t c = 0; c < L.keys.size(); ++c) {
+        hipStream_t lane = w.lanes[c];
+        if (hipStreamWaitEvent(lane, w.fork, 0) != hipSuccess)
+            return CZ_ERR_HIP;
+        czk::Queue q{};
+        q.fields = desc + L.first[c];
+        q.nfields = L.count[c];
+        q.ntickets = L.tickets[c];
+        q.ticket = counters + 2 * c;
+        q.status = counters + 2 * c + 1;
+        q.scratch = static_cast<uint8_t *>(w.scratch.ptr) + L.scratch_off[c];
+        if (czk::launch_prep(q, L.forward, lane) != hipSuccess)
+            return CZ_ERR_HIP;
+        if (L.tickets[c]) {
+            const hipError_t e = L.forward ? czk::launch_fwd(L.keys[c], q, L.grids[c], lane)
+                                           : czk::launch_inv(L.keys[c], q, L.grids[c], lane);
+            if (e != hipSuccess)
+                return CZ_ERR_HIP;
+        }
+        if (hipEventRecord(w.joins[c], lane) != hipSuccess || hipStreamWaitEvent(st, w.joins[c], 0) != hipSuccess)
+            return CZ_ERR_HIP;
+    }
+    if (czk::launch_fold_status(counters, (int)L.keys.size(), status, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    if (L.forward &&
+        hipMemcpyAsync(w.totals_host, w.totals.ptr, L.n * sizeof(uint64_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    return CZ_OK;
+}
+
+int check_batch_buffers(const Layout &L, const cz_params *ps, const void *const *srcs, const size_t *src_bytes,
+                        void *const *dsts, const size_t *dst_caps, size_t *need)
+{
+    for (int i = 0; i < L.n; ++i) {
+        const uint64_t nb = L.nblocks[i];
+        if (L.forward) {
+            if (dst_caps[i] < bound_of(ps[i], nb)) {
+                if (need)
+                    need[i] = (size_t)bound_of(ps[i], nb);
+                return CZ_ERR_CAPACITY;
+            }
+            if (!dsts[i] || (nb && !srcs[i]))
+                return CZ_ERR_ARG;
+        } else {
+            if (!srcs[i] || payload_start(nb) > src_bytes[i])
+                return CZ_ERR_FORMAT;
+            if ((uint64_t)ps[i].nx * ps[i].ny * ps[i].nz * ps[i].elem_bytes > dst_caps[i])
+                return CZ_ERR_CAPACITY;
+            if (nb && !dsts[i])
+                return CZ_ERR_ARG;
+        }
+    }
+    return CZ_OK;
 }
 
 }  // namespace
@@ -206,11 +511,12 @@ int cz_create(cz_ctx **out, int device)
     if (!ctx)
         return CZ_ERR_ARG;
     ctx->device = device;
-    if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-        hipMalloc(&ctx->work, sizeof(czk::CzWork)) != hipSuccess ||
-        hipMemset(ctx->work, 0, sizeof(czk::CzWork)) != hipSuccess ||
-        hipHostMalloc(&ctx->pinned, sizeof(czk::CzWork), hipHostMallocDefault) != hipSuccess ||
-        ensure_capacity(ctx, 4096) != CZ_OK) {
+    const bool ok = hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+                    hipMalloc(&ctx->work, sizeof(czk::CzWork)) == hipSuccess &&
+                    hipMemset(ctx->work, 0, sizeof(czk::CzWork)) == hipSuccess &&
+                    hipHostMalloc(&ctx->pinned, sizeof(czk::CzWork), hipHostMallocDefault) == hipSuccess &&
+                    ctx->flags.ensure(4096 * sizeof(uint64_t)) == CZ_OK && ctx->batch.init() == CZ_OK;
+    if (!ok) {
         cz_destroy(ctx);
         return CZ_ERR_HIP;
     }
@@ -224,14 +530,13 @@ void cz_destroy(cz_ctx *ctx)
         return;
     DeviceGuard guard(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->flags)
-        (void)hipFree(ctx->flags);
+    ctx->flags.release();
+    ctx->scratch.release();
+    ctx->batch.release();
     if (ctx->work)
         (void)hipFree(ctx->work);
     if (ctx->pinned)
         (void)hipHostFree(ctx->pinned);
-    if (ctx->scratch)
-        (void)hipFree(ctx->scratch);
     delete ctx;
 }
 
@@ -242,7 +547,7 @@ int cz_reserve(cz_ctx *ctx, uint64_t max_blocks)
     if (max_blocks >= MAX_BLOCKS)
         return CZ_ERR_SHAPE;
     DeviceGuard guard(ctx->device);
-    return ensure_capacity(ctx, max_blocks);
+    return ctx->flags.ensure(std::max<uint64_t>(max_blocks, 1) * sizeof(uint64_t));
 }
 
 size_t cz_compress_bound(const cz_params *p)
@@ -250,7 +555,22 @@ size_t cz_compress_bound(const cz_params *p)
     uint64_t nb = 0;
     if (check_params(p, &nb) != CZ_OK)
         return 0;
-    return (size_t)(payload_start(nb) + nb * record_bound(p->block, p->elem_bytes));
+    return (size_t)bound_of(*p, nb);
+}
+
+int cz_variant_count(uint32_t block, uint32_t elem_bytes)
+{
+    if (!supported_block(block) || (elem_bytes != 4 && elem_bytes != 8))
+        return 0;
+    return czk::variant_count(block, elem_bytes);
+}
+
+int cz_set_variant(cz_ctx *ctx, uint32_t block, uint32_t elem_bytes, uint32_t scheme, int variant)
+{
+    if (!ctx || scheme > 2 || variant < 0 || variant >= cz_variant_count(block, elem_bytes))
+        return CZ_ERR_ARG;
+    ctx->variant[block_index(block)][elem_bytes == 8][scheme] = (uint8_t)variant;
+    return CZ_OK;
 }
 
 int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_out, size_t out_cap,
@@ -262,7 +582,7 @@ int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_ou
     int rc = check_params(p, &nb);
     if (rc != CZ_OK)
         return rc;
-    const uint64_t bound = payload_start(nb) + nb * record_bound(p->block, p->elem_bytes);
+    const uint64_t bound = bound_of(*p, nb);
     if (out_cap < bound) {
         if (h_out_bytes)
             *h_out_bytes = (size_t)bound;
@@ -272,45 +592,25 @@ int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_ou
         return CZ_ERR_ARG;
     DeviceGuard guard(ctx->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if ((rc = ensure_capacity(ctx, nb)) != CZ_OK)
+    if ((rc = ctx->flags.ensure(std::max<uint64_t>(nb, 1) * sizeof(uint64_t))) != CZ_OK)
         return rc;
 
-    czk::PrepArgs pa{};
-    pa.out = static_cast<uint8_t *>(d_out);
-    pa.flags = ctx->flags;
-    pa.work = ctx->work;
-    pa.nblocks = nb;
-    pa.p0 = payload_start(nb);
-    build_header(p, nb, pa.header);
-    if (czk::launch_prep_fwd(pa, st) != hipSuccess)
+    czk::Queue q = work_queue(ctx);
+    q.ntickets = nb;
+    q.one = describe(*p, nb, true);
+    q.one.src = d_field;
+    q.one.dst = d_out;
+    q.one.flags = static_cast<uint64_t *>(ctx->flags.ptr);
+    q.one.total = &ctx->work->total;
+    if (czk::launch_prep(q, true, st) != hipSuccess)
         return CZ_ERR_HIP;
-
     if (nb) {
-        const czk::KernelKey key{p->block, p->scheme, p->elem_bytes};
-        czk::FwdArgs fa{};
-        fa.field = d_field;
-        fa.out = static_cast<uint8_t *>(d_out);
-        fa.offsets = reinterpret_cast<uint64_t *>(fa.out + HDR);
-        fa.flags = ctx->flags;
-        fa.work = ctx->work;
-        fa.nx = p->nx;
-        fa.ny = p->ny;
-        fa.nbx = p->nx / p->block;
-        fa.nby = p->ny / p->block;
-        fa.nblocks = nb;
-        fa.p0 = pa.p0;
-        fa.eps = p->epsilon;
-        fa.eps_f = (float)p->epsilon;  // round to nearest, then up if it fell below
-        if ((double)fa.eps_f < p->epsilon)
-            fa.eps_f = std::nextafter(fa.eps_f, INFINITY);
-        int grid = (int)nb;  // one workgroup per block up to 32^3
-        if (p->block == 64) {  // persistent, one scratch slot per workgroup
-            grid = grid_for(ctx, key, false, nb);
-            if ((rc = ensure_scratch(ctx, (size_t)grid * 64 * 64 * 64 * p->elem_bytes)) != CZ_OK)
-                return rc;
-            fa.scratch = ctx->scratch;
-        }
-        if (czk::launch_fwd(key, fa, grid, st) != hipSuccess)
+        const czk::KernelKey key = key_of(ctx, *p);
+        const int grid = grid_for(ctx, key, false, nb);
+        if ((rc = ctx->scratch.ensure(scratch_need(key, grid))) != CZ_OK)
+            return rc;
+        q.scratch = ctx->scratch.ptr;
+        if (czk::launch_fwd(key, q, grid, st) != hipSuccess)
             return CZ_ERR_HIP;
     }
     if (d_out_bytes &&
@@ -390,28 +690,21 @@ int cz_decompress(cz_ctx *ctx, const cz_params *expected, const void *d_in, size
         return CZ_ERR_CAPACITY;
     if (nb && !d_field)
         return CZ_ERR_ARG;
-    if (czk::launch_prep_inv(ctx->work, st) != hipSuccess)
+    czk::Queue q = work_queue(ctx);
+    q.ntickets = nb;
+    q.one = describe(p, nb, false);
+    q.one.src = d_in;
+    q.one.dst = d_field;
+    q.one.payload = total - p0;
+    if (czk::launch_prep(q, false, st) != hipSuccess)
         return CZ_ERR_HIP;
     if (nb) {
-        const czk::KernelKey key{p.block, p.scheme, p.elem_bytes};
-        czk::InvArgs ia{};
-        ia.in = static_cast<const uint8_t *>(d_in);
-        ia.field = d_field;
-        ia.work = ctx->work;
-        ia.nx = p.nx;
-        ia.ny = p.ny;
-        ia.nbx = p.nx / p.block;
-        ia.nby = p.ny / p.block;
-        ia.nblocks = nb;
-        ia.p0 = p0;
-        ia.payload = total - p0;
+        const czk::KernelKey key = key_of(ctx, p);
         const int grid = grid_for(ctx, key, true, nb);
-        if (p.block == 64) {
-            if ((rc = ensure_scratch(ctx, (size_t)grid * 64 * 64 * 64 * p.elem_bytes)) != CZ_OK)
-                return rc;
-            ia.scratch = ctx->scratch;
-        }
-        if (czk::launch_inv(key, ia, grid, st) != hipSuccess)
+        if ((rc = ctx->scratch.ensure(scratch_need(key, grid))) != CZ_OK)
+            return rc;
+        q.scratch = ctx->scratch.ptr;
+        if (czk::launch_inv(key, q, grid, st) != hipSuccess)
             return CZ_ERR_HIP;
     }
     if (sync) {
@@ -432,7 +725,7 @@ int cz_get_status(cz_ctx *ctx, void *stream)
     if (rc != CZ_OK)
         return rc;
     rc = status_to_error(ctx->pinned->status);
-    if (czk::launch_prep_inv(ctx->work, st) != hipSuccess)  // clears ticket and status
+    if (czk::launch_prep(work_queue(ctx), false, st) != hipSuccess)  // clears ticket and status
         return CZ_ERR_HIP;
     return rc;
 }
@@ -451,6 +744,159 @@ const char *cz_strerror(int code)
     case CZ_ERR_TIMEOUT: return "device-side wait exceeded its bound";
     default: return "unknown error";
     }
+}
+
+// ----------------------------------------------------------------- batches
+
+static int run_batch(cz_ctx *ctx, bool forward, int n, const cz_params *ps, const void *const *srcs,
+                     const size_t *src_bytes, void *const *dsts, const size_t *dst_caps, uint64_t *d_out_bytes,
+                     size_t *h_out_bytes, void *stream)
+{
+    if (!ctx || n < 0 || (n && (!ps || !srcs || !dsts || !dst_caps || (!forward && !src_bytes))))
+        return CZ_ERR_ARG;
+    if (n == 0)
+        return CZ_OK;
+    Layout L;
+    int rc = layout_batch(ctx, forward, n, ps, &L);
+    if (rc != CZ_OK)
+        return rc;
+    if ((rc = check_batch_buffers(L, ps, srcs, src_bytes, dsts, dst_caps, h_out_bytes)) != CZ_OK)
+        return rc;
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchWork &w = ctx->batch;
+    if ((rc = size_work(w, L)) != CZ_OK)
+        return rc;
+    if (hipEventSynchronize(w.staged) != hipSuccess)  // the previous upload has left the staging
+        return CZ_ERR_HIP;
+    stage_batch(w, L, ps, srcs, src_bytes, dsts);
+    if ((rc = enqueue_batch(w, L, &ctx->work->status, st)) != CZ_OK)
+        return rc;
+    if (hipEventRecord(w.staged, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    if (forward && d_out_bytes &&
+        hipMemcpyAsync(d_out_bytes, w.totals.ptr, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    if (forward && h_out_bytes) {
+        if ((rc = read_work(ctx, st)) != CZ_OK)
+            return rc;
+        for (int i = 0; i < n; ++i)
+            h_out_bytes[i] = (size_t)w.totals_host[i];
+        return take_status(ctx, st);
+    }
+    return CZ_OK;
+}
+
+int cz_compress_batch(cz_ctx *ctx, int n, const cz_params *ps, const void *const *d_fields, void *const *d_outs,
+                      const size_t *caps, uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream)
+{
+    return run_batch(ctx, true, n, ps, d_fields, nullptr, d_outs, caps, d_out_bytes, h_out_bytes, stream);
+}
+
+int cz_decompress_batch(cz_ctx *ctx, int n, const cz_params *ps, const void *const *d_ins, const size_t *in_bytes,
+                        void *const *d_fields, const size_t *caps, void *stream)
+{
+    return run_batch(ctx, false, n, ps, d_ins, in_bytes, d_fields, caps, nullptr, nullptr, stream);
+}
+
+// -------------------------------------------------------- captured plans
+
+int cz_plan_create(cz_ctx *ctx, int op, int n, const cz_params *ps, cz_plan **out)
+{
+    if (!ctx || !out || (op != 0 && op != 1) || n <= 0 || !ps)
+        return CZ_ERR_ARG;
+    *out = nullptr;
+    DeviceGuard guard(ctx->device);
+    cz_plan *plan = new (std::nothrow) cz_plan();
+    if (!plan)
+        return CZ_ERR_ARG;
+    plan->ctx = ctx;
+    plan->params.assign(ps, ps + n);
+    int rc = layout_batch(ctx, op == 0, n, ps, &plan->layout);
+    if (rc == CZ_OK)
+        rc = plan->work.init();
+    if (rc == CZ_OK)
+        rc = size_work(plan->work, plan->layout);
+    if (rc == CZ_OK && (hipEventCreateWithFlags(&plan->done, hipEventDisableTiming) != hipSuccess ||
+                        hipEventRecord(plan->done, nullptr) != hipSuccess))
+        rc = CZ_ERR_HIP;
+    if (rc != CZ_OK) {
+        cz_plan_destroy(plan);
+        return rc;
+    }
+    *out = plan;
+    return CZ_OK;
+}
+
+int cz_plan_run(cz_plan *plan, const void *const *srcs, const size_t *src_bytes, void *const *dsts,
+                const size_t *dst_caps, void *stream)
+{
+    if (!plan || !srcs || !dsts || !dst_caps || (!plan->layout.forward && !src_bytes))
+        return CZ_ERR_ARG;
+    const Layout &L = plan->layout;
+    int rc = check_batch_buffers(L, plan->params.data(), srcs, src_bytes, dsts, dst_caps, nullptr);
+    if (rc != CZ_OK)
+        return rc;
+    DeviceGuard guard(plan->ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipEventSynchronize(plan->done) != hipSuccess)  // the previous run has read the staging
+        return CZ_ERR_HIP;
+    stage_batch(plan->work, L, plan->params.data(), srcs, src_bytes, dsts);
+    if (!plan->exec) {
+        // capture on a private stream: upload, per-class lanes, join, status, sizes
+        hipStream_t cap = nullptr;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+            return CZ_ERR_HIP;
+        rc = CZ_OK;
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            rc = CZ_ERR_HIP;
+        if (rc == CZ_OK)
+            rc = enqueue_batch(plan->work, L, &plan->ctx->work->status, cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cap, &g);
+        if (rc == CZ_OK && e != hipSuccess)
+            rc = CZ_ERR_HIP;
+        if (rc == CZ_OK && hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0) != hipSuccess)
+            rc = CZ_ERR_HIP;
+        plan->graph = g;
+        (void)hipStreamDestroy(cap);
+        if (rc != CZ_OK)
+            return rc;
+    }
+    if (hipGraphLaunch(plan->exec, st) != hipSuccess || hipEventRecord(plan->done, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    return CZ_OK;
+}
+
+int cz_plan_result(cz_plan *plan, void *stream, size_t *h_out_bytes)
+{
+    if (!plan)
+        return CZ_ERR_ARG;
+    DeviceGuard guard(plan->ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = read_work(plan->ctx, st);
+    if (rc != CZ_OK)
+        return rc;
+    if (h_out_bytes && plan->layout.forward)
+        for (int i = 0; i < plan->layout.n; ++i)
+            h_out_bytes[i] = (size_t)plan->work.totals_host[i];
+    return take_status(plan->ctx, st);
+}
+
+void cz_plan_destroy(cz_plan *plan)
+{
+    if (!plan)
+        return;
+    DeviceGuard guard(plan->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (plan->exec)
+        (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph)
+        (void)hipGraphDestroy(plan->graph);
+    if (plan->done)
+        (void)hipEventDestroy(plan->done);
+    plan->work.release();
+    delete plan;
 }
 
 }  // extern "C"

@@ -1,6 +1,6 @@
-// Kernel-side interface of the wavelet-stage library: argument blocks, the
-// device workspace layout and the launchers (internal; the public ABI is
-// include/cz.h).
+// Kernel-side interface of the wavelet-stage library: the device work queue,
+// the per-field descriptors it points to, and the launchers (internal; the
+// public ABI is include/cz.h).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,10 +12,10 @@ namespace czk {
 // Threads per workgroup of the scratch-staged (N = 64) kernels.
 constexpr int SCRATCH_THREADS = 512;
 
-// Status bits latched by the kernels in CzWork::status.
+// Status bits latched by the kernels.
 enum : uint32_t { STATUS_NONFINITE = 1u, STATUS_FORMAT = 2u, STATUS_TIMEOUT = 4u };
 
-// Per-context device workspace header; the look-back flags follow it.
+// Per-context device workspace header (plain calls use its counters).
 struct CzWork {
     uint32_t ticket;  // next block ticket
     uint32_t status;  // STATUS_* bits of the current call
@@ -23,52 +23,57 @@ struct CzWork {
     uint64_t reserved[6];
 };
 
+// One field of a work queue.  Forward: src = field, dst = stream; inverse:
+// src = stream, dst = field.
+struct FieldDesc {
+    const void *src;
+    void *dst;
+    uint64_t *flags;      // forward: look-back flags, nblocks entries
+    uint64_t *total;      // forward: stream bytes, written by the last block (may be null)
+    uint32_t nx, ny, nbx, nby;
+    uint64_t nblocks;
+    uint64_t p0;          // payload start
+    uint64_t payload;     // inverse: payload bytes available
+    uint64_t first;       // the field's first ticket in its queue
+    double eps;
+    float eps_f;          // smallest float >= eps (the same test for float data)
+    uint32_t reserved;
+    uint32_t header[16];  // forward: the 64-byte header, payload size 0
+};
+
+// A device work queue: tickets [0, ntickets) map, in order, onto the blocks
+// of the fields (field f owns tickets [first_f, first_f + nblocks_f)).  A
+// single-field queue carries its descriptor inline (fields == nullptr).
+struct Queue {
+    const FieldDesc *fields;
+    uint32_t nfields;
+    uint32_t reserved;
+    uint64_t ntickets;
+    uint32_t *ticket;     // device ticket counter
+    uint32_t *status;     // device STATUS_* bits
+    void *scratch;        // N = 64: one N^3 slot of the field type per workgroup
+    FieldDesc one;
+};
+
 struct KernelKey {
     uint32_t block;       // N
     uint32_t scheme;      // W4 | W4LI | W3AI
     uint32_t elem_bytes;  // 4 | 8
+    uint32_t variant;     // tuning variant (see variant_count)
 };
 
-struct FwdArgs {
-    const void *field;   // [nz][ny][nx] of T
-    uint8_t *out;        // stream
-    uint64_t *offsets;   // out + 64
-    uint64_t *flags;     // look-back flags, nblocks entries, zeroed
-    CzWork *work;
-    uint32_t nx, ny, nbx, nby;
-    uint64_t nblocks;
-    uint64_t p0;         // payload start
-    double eps;
-    float eps_f;         // smallest float >= eps (the same test for float data)
-    void *scratch;       // N = 64: one N^3 slot of T per workgroup of the grid
-};
-
-struct InvArgs {
-    const uint8_t *in;   // stream
-    void *field;         // [nz][ny][nx] of T
-    CzWork *work;
-    uint32_t nx, ny, nbx, nby;
-    uint64_t nblocks;
-    uint64_t p0;
-    uint64_t payload;    // payload bytes from the header
-    void *scratch;       // N = 64: one N^3 slot of T per workgroup of the grid
-};
-
-struct PrepArgs {
-    uint8_t *out;
-    uint64_t *flags;
-    CzWork *work;
-    uint64_t nblocks;
-    uint64_t p0;
-    uint32_t header[16];  // the 64-byte header, payload size 0
-};
-
-hipError_t launch_fwd(const KernelKey &key, const FwdArgs &a, int grid, hipStream_t st);
-hipError_t launch_inv(const KernelKey &key, const InvArgs &a, int grid, hipStream_t st);
-hipError_t launch_prep_fwd(const PrepArgs &a, hipStream_t st);
-hipError_t launch_prep_inv(CzWork *work, hipStream_t st);
+hipError_t launch_fwd(const KernelKey &key, const Queue &q, int grid, hipStream_t st);
+hipError_t launch_inv(const KernelKey &key, const Queue &q, int grid, hipStream_t st);
+// Reset the queue's ticket and status; forward: clear each field's flags and
+// write its header, offset 0 and the pad before its payload.
+hipError_t launch_prep(const Queue &q, bool forward, hipStream_t st);
+// OR the status words of nclass (ticket, status) counter pairs into *status.
+hipError_t launch_fold_status(const uint32_t *counters, int nclass, uint32_t *status, hipStream_t st);
 // Resident workgroups per CU of the (fwd or inv) kernel for key.
 int occupancy(const KernelKey &key, bool inverse);
-int threads_per_block(const KernelKey &key);
+// Forward launches one workgroup per block up to 32^3 (grid = tickets).
+bool fwd_one_block_per_workgroup(const KernelKey &key);
+// Number of compiled shape variants for (block, elem_bytes).
+int variant_count(uint32_t block, uint32_t elem_bytes);
 
 }  // namespace czk

@@ -319,14 +319,14 @@ __device__ __forceinline__ void stage_lines(T *lds)
 // Decimation test |c| >= eps in double.  For float data this equals
 // |c| >= eps_f with eps_f the smallest float >= eps (computed on the host).
 template <typename T>
-__device__ __forceinline__ bool keep_test(T v, const FwdArgs &a);
+__device__ __forceinline__ bool keep_test(T v, const FieldDesc &a);
 template <>
-__device__ __forceinline__ bool keep_test<float>(float v, const FwdArgs &a)
+__device__ __forceinline__ bool keep_test<float>(float v, const FieldDesc &a)
 {
     return __builtin_fabsf(v) >= a.eps_f;
 }
 template <>
-__device__ __forceinline__ bool keep_test<double>(double v, const FwdArgs &a)
+__device__ __forceinline__ bool keep_test<double>(double v, const FieldDesc &a)
 {
     return __builtin_fabs(v) >= a.eps;
 }
@@ -334,14 +334,14 @@ __device__ __forceinline__ bool keep_test<double>(double v, const FwdArgs &a)
 // Issue the loads of slab group g of block b: planes [g Z, g Z + Z), one
 // coalesced row segment per plane and column.
 template <typename T, int N, int Z, int R>
-__device__ __forceinline__ void load_planes(const FwdArgs &a, uint64_t b, int g, uint32_t lane_off, T (*dst)[N])
+__device__ __forceinline__ void load_planes(const FieldDesc &a, uint64_t b, int g, uint32_t lane_off, T (*dst)[N])
 {
     using G = Geom<T, N, Z, R>;
     const size_t plane = (size_t)a.nx * a.ny;
     const uint32_t bx = (uint32_t)(b % a.nbx);
     const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
     const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
-    const T *blk = static_cast<const T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+    const T *blk = static_cast<const T *>(a.src) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
     const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
 #pragma unroll
     for (int j = 0; j < Z; ++j) {
@@ -352,31 +352,58 @@ __device__ __forceinline__ void load_planes(const FwdArgs &a, uint64_t b, int g,
     }
 }
 
+// The field that owns ticket t (fields hold consecutive ticket ranges).
+__device__ __forceinline__ uint32_t field_of_ticket(const Queue &q, uint64_t t)
+{
+    if (!q.fields)
+        return 0;
+    uint32_t lo = 0, hi = q.nfields - 1;  // last field whose range starts at or before t
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (q.fields[mid].first <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ const FieldDesc &field_desc(const Queue &q, uint32_t f)
+{
+    return q.fields ? q.fields[f] : q.one;
+}
+
 // One workgroup per block: the block's ticket is taken at workgroup start,
 // so every smaller ticket belongs to a workgroup that is resident or done and
 // the look-back always completes.
 template <typename T, int N, int S, int Z, int R, int ZP>
-__global__ __launch_bounds__(N *N / R) void fwd_kernel(FwdArgs a)
+__global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
 {
     using G = Geom<T, N, Z, R, ZP>;
     __shared__ T lds[G::LDS_ELEMS];
     __shared__ uint64_t s_words[G::WORDS];
     __shared__ uint32_t s_scan[G::WAVES + 1];
     __shared__ uint64_t s_block;
+    __shared__ uint32_t s_field;
     __shared__ uint64_t s_off;
 
     const int tid = threadIdx.x;
     const int x = tid % N, yq = tid / N;
     const uint32_t lane = lane_id();
     const int wave = tid / 64;
-    const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;  // element offset of (x, yq) in a z-plane
 
-    if (tid == 0)
-        s_block = atomicAdd(&a.work->ticket, 1u);
+    if (tid == 0) {
+        const uint64_t t = atomicAdd(q.ticket, 1u);
+        s_block = t;
+        s_field = t < q.ntickets ? field_of_ticket(q, t) : 0u;
+    }
     lds_barrier();
-    const uint64_t b = s_block;
-    if (b >= a.nblocks)
+    const uint64_t t = s_block;
+    if (t >= q.ntickets)
         return;
+    const FieldDesc &a = field_desc(q, s_field);
+    const uint64_t b = t - a.first;
+    const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;  // element offset of (x, yq) in a z-plane
 
     // load: for each z and r one coalesced row segment of N elements; the
     // rows of slab group g+1 stay in flight while group g is transformed
@@ -474,7 +501,7 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(FwdArgs a)
         keepbits[r] = kb;
     }
     if (bad)
-        atomicOr(&a.work->status, STATUS_NONFINITE);
+        atomicOr(q.status, STATUS_NONFINITE);
     // mask words: lane z R + r of each wavefront keeps the ballot of (z, r)
     uint64_t myword = 0;
 #pragma unroll
@@ -500,20 +527,22 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(FwdArgs a)
     const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
     const uint64_t rbytes = (used + 15ull) & ~15ull;
     if (tid == 0)
-        s_off = lookback(a.flags, b, rbytes, &a.work->status);
+        s_off = lookback(a.flags, b, rbytes, q.status);
     lds_barrier();
     const uint64_t off = s_off;
-    uint8_t *rec = a.out + a.p0 + off;
+    uint8_t *out = static_cast<uint8_t *>(a.dst);
+    uint8_t *rec = out + a.p0 + off;
 
     if (tid == 0) {
         reinterpret_cast<uint32_t *>(rec)[0] = nnz;
         reinterpret_cast<uint32_t *>(rec)[1] = 0u;
-        a.offsets[b + 1] = off + rbytes;
+        reinterpret_cast<uint64_t *>(out + 64)[b + 1] = off + rbytes;
         for (uint64_t p = used; p < rbytes; p += 4)
             *reinterpret_cast<uint32_t *>(rec + p) = 0u;
         if (b + 1 == a.nblocks) {
-            *reinterpret_cast<uint64_t *>(a.out + 56) = off + rbytes;
-            a.work->total = a.p0 + off + rbytes;
+            *reinterpret_cast<uint64_t *>(out + 56) = off + rbytes;
+            if (a.total)
+                *a.total = a.p0 + off + rbytes;
         }
     }
     uint64_t *mask = reinterpret_cast<uint64_t *>(rec + 8);
@@ -546,7 +575,7 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(FwdArgs a)
 // ------------------------------------------------------------------ inverse
 
 template <typename T, int N, int S, int Z, int R>
-__global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
+__global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
 {
     using G = Geom<T, N, Z, R>;
     __shared__ T lds[G::LDS_ELEMS];
@@ -554,44 +583,54 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
     __shared__ uint32_t s_pre[G::WORDS];
     __shared__ uint32_t s_scan[G::WAVES + 1];
     __shared__ uint64_t s_block;
+    __shared__ uint32_t s_field;
     __shared__ uint32_t s_ok;
 
     const int tid = threadIdx.x;
     const int x = tid % N, yq = tid / N;
     const uint32_t lane = lane_id();
     const int wave = tid / 64;
-    const size_t plane = (size_t)a.nx * a.ny;
-    const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;
-    const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
-    const uint64_t *offs = reinterpret_cast<const uint64_t *>(a.in + 64);
 
     while (true) {
         if (tid == 0) {
-            const uint64_t b = atomicAdd(&a.work->ticket, 1u);
-            s_block = b;
-            uint32_t ok = 0;
-            if (b < a.nblocks) {
+            const uint64_t t = atomicAdd(q.ticket, 1u);
+            uint32_t ok = 0, f = 0;
+            if (t < q.ntickets) {
+                f = field_of_ticket(q, t);
+                const FieldDesc &a = field_desc(q, f);
+                const uint8_t *in = static_cast<const uint8_t *>(a.src);
+                const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
+                const uint64_t b = t - a.first;
                 const uint64_t o0 = offs[b], o1 = offs[b + 1];
                 ok = o1 >= o0 && o1 <= a.payload && o1 - o0 >= 8ull + G::MASK_BYTES;
                 if (ok) {
-                    const uint32_t nnz = *reinterpret_cast<const uint32_t *>(a.in + a.p0 + o0);
+                    const uint32_t nnz = *reinterpret_cast<const uint32_t *>(in + a.p0 + o0);
                     const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
                     ok = nnz <= (uint32_t)(N * N * N) && ((used + 15ull) & ~15ull) == o1 - o0;
                 }
                 if (!ok)
-                    atomicOr(&a.work->status, STATUS_FORMAT);
+                    atomicOr(q.status, STATUS_FORMAT);
             }
+            s_block = t;
+            s_field = f;
             s_ok = ok;
         }
         lds_barrier();
-        const uint64_t b = s_block;
-        if (b >= a.nblocks)
+        const uint64_t t = s_block;
+        if (t >= q.ntickets)
             break;
         if (!s_ok) {
             lds_barrier();
             continue;
         }
-        const uint8_t *rec = a.in + a.p0 + offs[b];
+        const FieldDesc &a = field_desc(q, s_field);
+        const uint64_t b = t - a.first;
+        const size_t plane = (size_t)a.nx * a.ny;
+        const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;
+        const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
+        const uint8_t *in = static_cast<const uint8_t *>(a.src);
+        const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
+        const uint8_t *rec = in + a.p0 + offs[b];
         const uint32_t nnz = *reinterpret_cast<const uint32_t *>(rec);
         const uint64_t *mask = reinterpret_cast<const uint64_t *>(rec + 8);
         const rsrc_t vr = make_rsrc(rec + 8 + G::MASK_BYTES, nnz * (uint32_t)sizeof(T));
@@ -606,7 +645,7 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
         lds_barrier();
         if (s_scan[G::WAVES] != nnz) {
             if (tid == 0)
-                atomicOr(&a.work->status, STATUS_FORMAT);
+                atomicOr(q.status, STATUS_FORMAT);
             lds_barrier();
             continue;
         }
@@ -657,7 +696,7 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(InvArgs a)
         const uint32_t bx = (uint32_t)(b % a.nbx);
         const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
         const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
-        T *blk = static_cast<T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+        T *blk = static_cast<T *>(a.dst) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
 #pragma unroll
         for (int g = 0; g < N / Z; ++g) {
 #pragma unroll
@@ -777,7 +816,7 @@ __device__ __forceinline__ uint32_t scan_words(const uint64_t *s_words, uint32_t
 }
 
 template <typename T, int N, int S>
-__global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(FwdArgs a)
+__global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
 {
     constexpr int NT = SCRATCH_THREADS;
     constexpr int WORDS = N * N * N / 64;
@@ -787,43 +826,48 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(FwdArgs a)
     __shared__ uint32_t s_pre[WORDS];
     __shared__ uint32_t s_scan[WAVES + 1];
     __shared__ uint64_t s_block;
+    __shared__ uint32_t s_field;
     __shared__ uint64_t s_off;
     __shared__ uint32_t s_bad;
 
     const int tid = threadIdx.x;
     const uint32_t lane = lane_id();
     const int wave = tid / 64;
-    const size_t plane = (size_t)a.nx * a.ny;
-    T *blkS = static_cast<T *>(a.scratch) + (size_t)blockIdx.x * N * N * N;
+    T *blkS = static_cast<T *>(q.scratch) + (size_t)blockIdx.x * N * N * N;
 
     while (true) {
         if (tid == 0) {
-            s_block = atomicAdd(&a.work->ticket, 1u);
+            const uint64_t t = atomicAdd(q.ticket, 1u);
+            s_block = t;
+            s_field = t < q.ntickets ? field_of_ticket(q, t) : 0u;
             s_bad = 0;
         }
         gbarrier<NT>();
-        const uint64_t b = s_block;
-        if (b >= a.nblocks)
+        const uint64_t t = s_block;
+        if (t >= q.ntickets)
             break;
+        const FieldDesc &a = field_desc(q, s_field);
+        const uint64_t b = t - a.first;
+        const size_t plane = (size_t)a.nx * a.ny;
         const uint32_t bx = (uint32_t)(b % a.nbx);
         const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
         const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
-        const T *src = static_cast<const T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+        const T *src = static_cast<const T *>(a.src) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
         bool bad = false;
-        for (int q = tid; q < N * N * N; q += NT) {
-            const int x = q % N, y = (q / N) % N, z = q / (N * N);
+        for (int qq = tid; qq < N * N * N; qq += NT) {
+            const int x = qq % N, y = (qq / N) % N, z = qq / (N * N);
             const T v = src[(size_t)z * plane + (size_t)y * a.nx + x];
             bad |= !finite(v);
-            blkS[q] = v;
+            blkS[qq] = v;
         }
         gbarrier<NT>();
         scratch_levels_fwd<T, S, N, N, NT>(blkS);
 
         // decimation: wavefront w takes words w, w + WAVES, ...
         for (int w = wave; w < WORDS; w += WAVES) {
-            const int q = w * 64 + (int)lane;
-            const int x = q % N, y = (q / N) % N, z = q / (N * N);
-            const T v = blkS[q];
+            const int qq = w * 64 + (int)lane;
+            const int x = qq % N, y = (qq / N) % N, z = qq / (N * N);
+            const T v = blkS[qq];
             bad |= !finite(v);
             const bool keep = (x < 4 && y < 4 && z < 4) || keep_test<T>(v, a);
             const uint64_t m = __ballot(keep);
@@ -834,24 +878,26 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(FwdArgs a)
             s_bad = 1;
         gbarrier<NT>();
         if (tid == 0 && s_bad)
-            atomicOr(&a.work->status, STATUS_NONFINITE);
+            atomicOr(q.status, STATUS_NONFINITE);
         const uint32_t nnz = scan_words<NT, WORDS>(s_words, s_pre, s_scan);
         const uint64_t used = 8ull + MASK_BYTES + (uint64_t)nnz * sizeof(T);
         const uint64_t rbytes = (used + 15ull) & ~15ull;
         if (tid == 0)
-            s_off = lookback(a.flags, b, rbytes, &a.work->status);
+            s_off = lookback(a.flags, b, rbytes, q.status);
         gbarrier<NT>();
         const uint64_t off = s_off;
-        uint8_t *rec = a.out + a.p0 + off;
+        uint8_t *out = static_cast<uint8_t *>(a.dst);
+        uint8_t *rec = out + a.p0 + off;
         if (tid == 0) {
             reinterpret_cast<uint32_t *>(rec)[0] = nnz;
             reinterpret_cast<uint32_t *>(rec)[1] = 0u;
-            a.offsets[b + 1] = off + rbytes;
+            reinterpret_cast<uint64_t *>(out + 64)[b + 1] = off + rbytes;
             for (uint64_t p = used; p < rbytes; p += 4)
                 *reinterpret_cast<uint32_t *>(rec + p) = 0u;
             if (b + 1 == a.nblocks) {
-                *reinterpret_cast<uint64_t *>(a.out + 56) = off + rbytes;
-                a.work->total = a.p0 + off + rbytes;
+                *reinterpret_cast<uint64_t *>(out + 56) = off + rbytes;
+                if (a.total)
+                    *a.total = a.p0 + off + rbytes;
             }
         }
         uint64_t *mask = reinterpret_cast<uint64_t *>(rec + 8);
@@ -868,7 +914,7 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(FwdArgs a)
 }
 
 template <typename T, int N, int S>
-__global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(InvArgs a)
+__global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
 {
     constexpr int NT = SCRATCH_THREADS;
     constexpr int WORDS = N * N * N / 64;
@@ -878,42 +924,52 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(InvArgs a)
     __shared__ uint32_t s_pre[WORDS];
     __shared__ uint32_t s_scan[WAVES + 1];
     __shared__ uint64_t s_block;
+    __shared__ uint32_t s_field;
     __shared__ uint32_t s_ok;
 
     const int tid = threadIdx.x;
     const uint32_t lane = lane_id();
     const int wave = tid / 64;
-    const size_t plane = (size_t)a.nx * a.ny;
-    const uint64_t *offs = reinterpret_cast<const uint64_t *>(a.in + 64);
-    T *blkS = static_cast<T *>(a.scratch) + (size_t)blockIdx.x * N * N * N;
+    T *blkS = static_cast<T *>(q.scratch) + (size_t)blockIdx.x * N * N * N;
 
     while (true) {
         if (tid == 0) {
-            const uint64_t b = atomicAdd(&a.work->ticket, 1u);
-            s_block = b;
-            uint32_t ok = 0;
-            if (b < a.nblocks) {
+            const uint64_t t = atomicAdd(q.ticket, 1u);
+            uint32_t ok = 0, f = 0;
+            if (t < q.ntickets) {
+                f = field_of_ticket(q, t);
+                const FieldDesc &a = field_desc(q, f);
+                const uint8_t *in = static_cast<const uint8_t *>(a.src);
+                const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
+                const uint64_t b = t - a.first;
                 const uint64_t o0 = offs[b], o1 = offs[b + 1];
                 ok = o1 >= o0 && o1 <= a.payload && o1 - o0 >= 8ull + MASK_BYTES;
                 if (ok) {
-                    const uint32_t nnz = *reinterpret_cast<const uint32_t *>(a.in + a.p0 + o0);
+                    const uint32_t nnz = *reinterpret_cast<const uint32_t *>(in + a.p0 + o0);
                     const uint64_t used = 8ull + MASK_BYTES + (uint64_t)nnz * sizeof(T);
                     ok = nnz <= (uint32_t)(N * N * N) && ((used + 15ull) & ~15ull) == o1 - o0;
                 }
                 if (!ok)
-                    atomicOr(&a.work->status, STATUS_FORMAT);
+                    atomicOr(q.status, STATUS_FORMAT);
             }
+            s_block = t;
+            s_field = f;
             s_ok = ok;
         }
         gbarrier<NT>();
-        const uint64_t b = s_block;
-        if (b >= a.nblocks)
+        const uint64_t t = s_block;
+        if (t >= q.ntickets)
             break;
         if (!s_ok) {
             gbarrier<NT>();
             continue;
         }
-        const uint8_t *rec = a.in + a.p0 + offs[b];
+        const FieldDesc &a = field_desc(q, s_field);
+        const uint64_t b = t - a.first;
+        const size_t plane = (size_t)a.nx * a.ny;
+        const uint8_t *in = static_cast<const uint8_t *>(a.src);
+        const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
+        const uint8_t *rec = in + a.p0 + offs[b];
         const uint32_t nnz = *reinterpret_cast<const uint32_t *>(rec);
         const uint64_t *mask = reinterpret_cast<const uint64_t *>(rec + 8);
         const rsrc_t vr = make_rsrc(rec + 8 + MASK_BYTES, nnz * (uint32_t)sizeof(T));
@@ -924,7 +980,7 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(InvArgs a)
         gbarrier<NT>();
         if (total != nnz) {
             if (tid == 0)
-                atomicOr(&a.work->status, STATUS_FORMAT);
+                atomicOr(q.status, STATUS_FORMAT);
             gbarrier<NT>();
             continue;
         }
@@ -940,10 +996,10 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(InvArgs a)
         const uint32_t bx = (uint32_t)(b % a.nbx);
         const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
         const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
-        T *dst = static_cast<T *>(a.field) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
-        for (int q = tid; q < N * N * N; q += NT) {
-            const int x = q % N, y = (q / N) % N, z = q / (N * N);
-            dst[(size_t)z * plane + (size_t)y * a.nx + x] = blkS[q];
+        T *dst = static_cast<T *>(a.dst) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+        for (int qq = tid; qq < N * N * N; qq += NT) {
+            const int x = qq % N, y = (qq / N) % N, z = qq / (N * N);
+            dst[(size_t)z * plane + (size_t)y * a.nx + x] = blkS[qq];
         }
         gbarrier<NT>();
     }
@@ -951,161 +1007,179 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(InvArgs a)
 
 // ------------------------------------------------------------- bookkeeping
 
-// Reset the ticket and status, clear the look-back flags, write the header
-// (payload size 0 until the last block fills it), off[0] and the zero pad
-// between the offset table and the payload.
-__global__ void prep_fwd_kernel(PrepArgs a)
+// Reset the queue's ticket and status.  Forward: for every field (y index
+// of the grid) clear its look-back flags and write its header (payload size
+// 0 until its last block fills it), offset 0 and the zero pad between its
+// offset table and payload; a field without blocks gets its total here.
+__global__ void prep_kernel(Queue q, int forward)
 {
     const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    if (i0 == 0 && blockIdx.y == 0) {
+        *q.ticket = 0;
+        *q.status = 0;
+    }
+    if (!forward)
+        return;
+    const FieldDesc &a = field_desc(q, blockIdx.y);
+    uint8_t *out = static_cast<uint8_t *>(a.dst);
     for (uint64_t i = i0; i < a.nblocks; i += stride)
         a.flags[i] = 0;
     if (i0 == 0) {
-        a.work->ticket = 0;
-        a.work->status = 0;
-        a.work->total = a.nblocks == 0 ? a.p0 : 0;
-        uint32_t *h = reinterpret_cast<uint32_t *>(a.out);
+        uint32_t *h = reinterpret_cast<uint32_t *>(out);
         for (int k = 0; k < 16; ++k)
             h[k] = a.header[k];
-        reinterpret_cast<uint64_t *>(a.out + 64)[0] = 0;
+        reinterpret_cast<uint64_t *>(out + 64)[0] = 0;
+        if (a.nblocks == 0 && a.total)
+            *a.total = a.p0;
     }
     const uint64_t pad0 = 64 + 8 * (a.nblocks + 1);
     for (uint64_t p = pad0 + 4 * i0; p < a.p0; p += 4 * stride)
-        *reinterpret_cast<uint32_t *>(a.out + p) = 0u;
+        *reinterpret_cast<uint32_t *>(out + p) = 0u;
 }
 
-__global__ void prep_inv_kernel(CzWork *work)
+// OR the status words of a batch's classes (ticket, status pairs) into one.
+__global__ void fold_status_kernel(const uint32_t *counters, int nclass, uint32_t *status)
 {
     if (threadIdx.x == 0) {
-        work->ticket = 0;
-        work->status = 0;
+        uint32_t bits = 0;
+        for (int c = 0; c < nclass; ++c)
+            bits |= counters[2 * c + 1];
+        if (bits)
+            atomicOr(status, bits);
     }
 }
 
 // ----------------------------------------------------------------- dispatch
 
-// Shape per (precision, N): slab depth Z and columns per thread R.  Float
-// blocks and double blocks up to 16^3 are staged whole in LDS with one column
-// per thread; a double 32^3 block (256 KiB) is staged 16 slabs at a time
-// (132 KiB of the 160 KiB LDS) with two columns per thread, so the 512-thread
-// workgroup has 256 VGPRs per lane for the half-block it keeps in registers.
-template <typename T, int N>
+// Shape per (precision, N, variant): slab depth Z, columns per thread R and
+// (forward) planes kept in VGPRs ZP.
+//   variant 0: float blocks and double blocks up to 16^3 staged whole in LDS,
+//     one column per thread; a double 32^3 block (256 KiB) staged 16 slabs at a
+//     time (132 KiB of LDS) with two columns per thread (512 threads, 256
+//     VGPRs a lane).  After the finest level the double 32^3 path parks 14
+//     planes (118 KiB + the 35 KiB coarse region), float 32^3 parks 16.
+//   variant 1: half the slab depth (N = 16, 32); float 32^3 with two columns
+//     per thread.
+template <typename T, int N, int V>
 struct Shape {
     static constexpr bool big = sizeof(T) == 8 && N >= 32;
-    static constexpr int Z = big ? N / 2 : N;
-    static constexpr int R = big ? 2 : 1;
-    // forward: planes kept in VGPRs after the finest level (the rest parked in
-    // LDS): double 32^3 parks 14 planes (118 KiB + 35 KiB coarse region), float
-    // 32^3 parks 16 (66 KiB + 17 KiB); smaller blocks park nothing
+    static constexpr int Z = (V == 1 && N >= 16) ? (big ? N / 4 : N / 2) : (big ? N / 2 : N);
+    static constexpr int R = (big || (V == 1 && N == 32)) ? 2 : 1;
     static constexpr int ZP = N < 32 ? N : (big ? N / 2 + 2 : N / 2);
+    static constexpr int NT = N * N / R;
 };
 
-template <typename T, int N, int S>
-static hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t st)
+template <typename T, int N, int S, int V>
+static hipError_t launch_fwd_t(const Queue &q, int grid, hipStream_t st)
 {
-    using P = Shape<T, N>;
-    hipLaunchKernelGGL((fwd_kernel<T, N, S, P::Z, P::R, P::ZP>), dim3(grid), dim3(N * N / P::R), 0, st, a);
+    using P = Shape<T, N, V>;
+    hipLaunchKernelGGL((fwd_kernel<T, N, S, P::Z, P::R, P::ZP>), dim3(grid), dim3(P::NT), 0, st, q);
     return hipGetLastError();
 }
 
-template <typename T, int N, int S>
-static hipError_t launch_inv_t(const InvArgs &a, int grid, hipStream_t st)
+template <typename T, int N, int S, int V>
+static hipError_t launch_inv_t(const Queue &q, int grid, hipStream_t st)
 {
-    using P = Shape<T, N>;
-    hipLaunchKernelGGL((inv_kernel<T, N, S, P::Z, P::R>), dim3(grid), dim3(N * N / P::R), 0, st, a);
+    using P = Shape<T, N, V>;
+    hipLaunchKernelGGL((inv_kernel<T, N, S, P::Z, P::R>), dim3(grid), dim3(P::NT), 0, st, q);
     return hipGetLastError();
 }
 
-template <typename T, int N, int S>
+template <typename T, int N, int S, int V>
 static int occupancy_t(bool inverse)
 {
-    using P = Shape<T, N>;
+    using P = Shape<T, N, V>;
     int nb = 0;
     hipError_t e =
-        inverse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, inv_kernel<T, N, S, P::Z, P::R>, N * N / P::R, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<T, N, S, P::Z, P::R, P::ZP>, N * N / P::R, 0);
+        inverse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, inv_kernel<T, N, S, P::Z, P::R>, P::NT, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<T, N, S, P::Z, P::R, P::ZP>, P::NT, 0);
     return e == hipSuccess ? nb : 0;
 }
 
-int threads_per_block(const KernelKey &key)
+template <typename T, int S>
+static hipError_t launch_fwd_scratch_t(const Queue &q, int grid, hipStream_t st)
 {
-    if (key.block == 64)
-        return SCRATCH_THREADS;
-    const bool big = key.elem_bytes == 8 && key.block >= 32;
-    return (int)(key.block * key.block) / (big ? 2 : 1);
+    hipLaunchKernelGGL((fwd_scratch_kernel<T, 64, S>), dim3(grid), dim3(SCRATCH_THREADS), 0, st, q);
+    return hipGetLastError();
 }
 
+template <typename T, int S>
+static hipError_t launch_inv_scratch_t(const Queue &q, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((inv_scratch_kernel<T, 64, S>), dim3(grid), dim3(SCRATCH_THREADS), 0, st, q);
+    return hipGetLastError();
+}
+
+template <typename T, int S>
+static hipError_t scratch_dispatch(bool inverse, const Queue &q, int grid, hipStream_t st)
+{
+    return inverse ? launch_inv_scratch_t<T, S>(q, grid, st) : launch_fwd_scratch_t<T, S>(q, grid, st);
+}
+
+// (T, N, S, V) -> OP<T, N, S, V> ARGS for the on-chip block sizes.
+#define CZ_SCHEMES(T, N, V, OP, ARGS)                                                                         \
+    switch (key.scheme) {                                                                                    \
+    case W4: return OP<T, N, W4, V> ARGS;                                                                    \
+    case W4LI: return OP<T, N, W4LI, V> ARGS;                                                                \
+    default: return OP<T, N, W3AI, V> ARGS;                                                                  \
+    }
+#define CZ_VARIANTS(T, N, OP, ARGS)                                                                           \
+    if (key.variant == 1) {                                                                                  \
+        CZ_SCHEMES(T, N, 1, OP, ARGS)                                                                        \
+    } else {                                                                                                 \
+        CZ_SCHEMES(T, N, 0, OP, ARGS)                                                                        \
+    }
 #define CZ_DISPATCH(T, OP, ARGS)                                                                              \
     switch (key.block) {                                                                                     \
-    case 8:                                                                                                  \
-        switch (key.scheme) {                                                                                \
-        case W4: return OP<T, 8, W4> ARGS;                                           \
-        case W4LI: return OP<T, 8, W4LI> ARGS;                                       \
-        default: return OP<T, 8, W3AI> ARGS;                                         \
-        }                                                                                                    \
-    case 16:                                                                                                 \
-        switch (key.scheme) {                                                                                \
-        case W4: return OP<T, 16, W4> ARGS;                                         \
-        case W4LI: return OP<T, 16, W4LI> ARGS;                                     \
-        default: return OP<T, 16, W3AI> ARGS;                                       \
-        }                                                                                                    \
-    default:                                                                                                 \
-        switch (key.scheme) {                                                                                \
-        case W4: return OP<T, 32, W4> ARGS;                                         \
-        case W4LI: return OP<T, 32, W4LI> ARGS;                                     \
-        default: return OP<T, 32, W3AI> ARGS;                                       \
-        }                                                                                                    \
+    case 8: CZ_SCHEMES(T, 8, 0, OP, ARGS)                                                                    \
+    case 16: CZ_VARIANTS(T, 16, OP, ARGS)                                                                    \
+    default: CZ_VARIANTS(T, 32, OP, ARGS)                                                                    \
     }
 
-template <typename T, int S>
-static hipError_t launch_fwd_scratch_t(const FwdArgs &a, int grid, hipStream_t st)
-{
-    hipLaunchKernelGGL((fwd_scratch_kernel<T, 64, S>), dim3(grid), dim3(SCRATCH_THREADS), 0, st, a);
-    return hipGetLastError();
-}
-
-template <typename T, int S>
-static hipError_t launch_inv_scratch_t(const InvArgs &a, int grid, hipStream_t st)
-{
-    hipLaunchKernelGGL((inv_scratch_kernel<T, 64, S>), dim3(grid), dim3(SCRATCH_THREADS), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_fwd(const KernelKey &key, const FwdArgs &a, int grid, hipStream_t st)
+hipError_t launch_fwd(const KernelKey &key, const Queue &q, int grid, hipStream_t st)
 {
     if (key.block == 64) {
-        const bool f = key.elem_bytes == 4;
+        if (key.elem_bytes == 4) {
+            switch (key.scheme) {
+            case W4: return scratch_dispatch<float, W4>(false, q, grid, st);
+            case W4LI: return scratch_dispatch<float, W4LI>(false, q, grid, st);
+            default: return scratch_dispatch<float, W3AI>(false, q, grid, st);
+            }
+        }
         switch (key.scheme) {
-        case W4: return f ? launch_fwd_scratch_t<float, W4>(a, grid, st) : launch_fwd_scratch_t<double, W4>(a, grid, st);
-        case W4LI:
-            return f ? launch_fwd_scratch_t<float, W4LI>(a, grid, st) : launch_fwd_scratch_t<double, W4LI>(a, grid, st);
-        default:
-            return f ? launch_fwd_scratch_t<float, W3AI>(a, grid, st) : launch_fwd_scratch_t<double, W3AI>(a, grid, st);
+        case W4: return scratch_dispatch<double, W4>(false, q, grid, st);
+        case W4LI: return scratch_dispatch<double, W4LI>(false, q, grid, st);
+        default: return scratch_dispatch<double, W3AI>(false, q, grid, st);
         }
     }
     if (key.elem_bytes == 4) {
-        CZ_DISPATCH(float, launch_fwd_t, (a, grid, st))
+        CZ_DISPATCH(float, launch_fwd_t, (q, grid, st))
     } else {
-        CZ_DISPATCH(double, launch_fwd_t, (a, grid, st))
+        CZ_DISPATCH(double, launch_fwd_t, (q, grid, st))
     }
 }
 
-hipError_t launch_inv(const KernelKey &key, const InvArgs &a, int grid, hipStream_t st)
+hipError_t launch_inv(const KernelKey &key, const Queue &q, int grid, hipStream_t st)
 {
     if (key.block == 64) {
-        const bool f = key.elem_bytes == 4;
+        if (key.elem_bytes == 4) {
+            switch (key.scheme) {
+            case W4: return scratch_dispatch<float, W4>(true, q, grid, st);
+            case W4LI: return scratch_dispatch<float, W4LI>(true, q, grid, st);
+            default: return scratch_dispatch<float, W3AI>(true, q, grid, st);
+            }
+        }
         switch (key.scheme) {
-        case W4: return f ? launch_inv_scratch_t<float, W4>(a, grid, st) : launch_inv_scratch_t<double, W4>(a, grid, st);
-        case W4LI:
-            return f ? launch_inv_scratch_t<float, W4LI>(a, grid, st) : launch_inv_scratch_t<double, W4LI>(a, grid, st);
-        default:
-            return f ? launch_inv_scratch_t<float, W3AI>(a, grid, st) : launch_inv_scratch_t<double, W3AI>(a, grid, st);
+        case W4: return scratch_dispatch<double, W4>(true, q, grid, st);
+        case W4LI: return scratch_dispatch<double, W4LI>(true, q, grid, st);
+        default: return scratch_dispatch<double, W3AI>(true, q, grid, st);
         }
     }
     if (key.elem_bytes == 4) {
-        CZ_DISPATCH(float, launch_inv_t, (a, grid, st))
+        CZ_DISPATCH(float, launch_inv_t, (q, grid, st))
     } else {
-        CZ_DISPATCH(double, launch_inv_t, (a, grid, st))
+        CZ_DISPATCH(double, launch_inv_t, (q, grid, st))
     }
 }
 
@@ -1120,19 +1194,28 @@ int occupancy(const KernelKey &key, bool inverse)
     }
 }
 
-hipError_t launch_prep_fwd(const PrepArgs &a, hipStream_t st)
+bool fwd_one_block_per_workgroup(const KernelKey &key) { return key.block <= 32; }
+
+int variant_count(uint32_t block, uint32_t elem_bytes)
 {
-    uint64_t need = a.nblocks > 0 ? a.nblocks : 1;
-    int grid = (int)((need + 255) / 256);
-    if (grid > 1024)
-        grid = 1024;
-    hipLaunchKernelGGL(prep_fwd_kernel, dim3(grid), dim3(256), 0, st, a);
+    (void)elem_bytes;
+    return (block == 16 || block == 32) ? 2 : 1;
+}
+
+hipError_t launch_fold_status(const uint32_t *counters, int nclass, uint32_t *status, hipStream_t st)
+{
+    hipLaunchKernelGGL(fold_status_kernel, dim3(1), dim3(64), 0, st, counters, nclass, status);
     return hipGetLastError();
 }
 
-hipError_t launch_prep_inv(CzWork *work, hipStream_t st)
+hipError_t launch_prep(const Queue &q, bool forward, hipStream_t st)
 {
-    hipLaunchKernelGGL(prep_inv_kernel, dim3(1), dim3(64), 0, st, work);
+    // enough threads in x to clear the largest field's flags in a few passes
+    const uint64_t most = forward && q.ntickets > 0 ? q.ntickets : 1;
+    int gx = (int)((most + 255) / 256);
+    if (gx > 1024)
+        gx = 1024;
+    hipLaunchKernelGGL(prep_kernel, dim3(gx, forward ? q.nfields : 1), dim3(256), 0, st, q, forward ? 1 : 0);
     return hipGetLastError();
 }
 
