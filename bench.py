@@ -161,12 +161,138 @@ def traffic_record(kernel: str):
     return rec.get("kernels", {}).get(kernel)
 
 
+def c4_fields(device):
+    """24 fields of mixed edge, block size, precision and scheme: edge from
+    {96, 160, 256, 384, 512, 768}, N from {16, 32, 64} redrawn until it divides
+    the edge, float32/float64 at even odds, scheme uniform; bubble clouds for
+    even i, Gaussian bumps for odd i; seed 1906000 + i; eps 1e-3 of range."""
+    import numpy as np
+    import torch
+
+    from paper_1903_07761_amd import fields as G
+
+    items = []
+    for i in range(24):
+        rng = np.random.Generator(np.random.PCG64(1906 * 1000 + i))
+        edge = int(rng.choice([96, 160, 256, 384, 512, 768]))
+        N = int(rng.choice([16, 32, 64]))
+        while edge % N:
+            N = int(rng.choice([16, 32, 64]))
+        dt = torch.float32 if rng.random() < 0.5 else torch.float64
+        scheme = ["W4", "W4_li", "W3_ai"][int(rng.integers(0, 3))]
+        seed = 1906 * 1000 + i
+        if i % 2 == 0:
+            f = G.bubble_cloud(edge, seed, dtype=dt, device=device)
+        else:
+            f = G.gaussian_bumps(edge, seed, dtype=dt, device=device)
+        items.append((f"f{i}", f, scheme, N, 1e-3 * G.value_range(f)))
+        log(f"c4 field {i}: {edge}^3 {dt} N={N} {scheme}")
+    return items
+
+
+def main_c4(args):
+    """Mixed batch: 24 single-field launches against one batched call (and its
+    captured plan); streams and reconstructions must be identical."""
+    import torch
+
+    from paper_1903_07761_amd.codec import Codec
+
+    dev = torch.device("cuda", 0)
+    codec = Codec(0)
+    items = c4_fields(dev)
+    st = torch.cuda.current_stream(dev)
+    n = len(items)
+    ps = [codec.params(t, N, s, e) for _, t, s, N, e in items]
+    caps = [codec.bound(t.shape, t.dtype, N) for _, t, _, N, _ in items]
+    raw_total = sum(t.numel() * t.element_size() for _, t, _, _, _ in items)
+    bufs = {k: [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps] for k in ("plain", "batch", "plan")}
+    recs = {k: [torch.empty_like(t) for _, t, _, _, _ in items] for k in ("plain", "batch", "plan")}
+    sizes = {k: torch.zeros(n, dtype=torch.int64, device=dev) for k in ("plain", "batch")}
+    codec.ctx.reserve(max(t.numel() // N ** 3 for _, t, _, N, _ in items))
+    fields = [t for _, t, _, _, _ in items]
+    plan_c = codec.plan("compress", ps)
+    plan_d = codec.plan("decompress", ps)
+    sh = st.cuda_stream
+
+    def plain():
+        for i, (_, t, s, N, e) in enumerate(items):
+            codec.compress(t, N, s, e, out=bufs["plain"][i], sync=False, out_bytes=sizes["plain"][i:i + 1])
+            codec.decompress(bufs["plain"][i], caps[i], out=recs["plain"][i], expected=ps[i])
+
+    def batch():
+        codec.compress_batch(fields, [N for _, _, _, N, _ in items], [s for _, _, s, _, _ in items],
+                             [e for _, _, _, _, e in items], outs=bufs["batch"], sync=False,
+                             out_bytes=sizes["batch"])
+        codec.decompress_batch(bufs["batch"], caps, ps, outs=recs["batch"])
+
+    def plan():
+        plan_c.run([t.data_ptr() for t in fields], [b.data_ptr() for b in bufs["plan"]], caps, stream=sh)
+        plan_d.run([b.data_ptr() for b in bufs["plan"]], [r.data_ptr() for r in recs["plan"]],
+                   [r.numel() * r.element_size() for r in recs["plan"]], src_bytes=caps, stream=sh)
+
+    res = {}
+    for name, fn in (("plain", plain), ("batch", batch), ("plan", plan)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(args.steps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        rc = codec.status()
+        if rc != 0:
+            raise SystemExit(f"device status {rc} after {name}")
+        ms = e0.elapsed_time(e1) / args.steps
+        res[name] = {"ms_per_step": round(ms, 3), "GBps": round(raw_total / (ms / 1e3) / 1e9, 2)}
+        log(f"c4 {name}: {ms:.3f} ms per step")
+    plan_sizes = plan_c.result(stream=sh)
+
+    log("c4 identity check")
+    sp, sb = sizes["plain"].cpu().tolist(), sizes["batch"].cpu().tolist()
+    identical = sp == sb == plan_sizes
+    for i in range(n):
+        k = sp[i]
+        identical &= bool(torch.equal(bufs["plain"][i][:k], bufs["batch"][i][:k]))
+        identical &= bool(torch.equal(bufs["plain"][i][:k], bufs["plan"][i][:k]))
+        for other in ("batch", "plan"):
+            identical &= bool(torch.equal(recs["plain"][i].view(torch.uint8), recs[other][i].view(torch.uint8)))
+    classes = sorted({(N, str(t.dtype).replace("torch.", ""), s) for _, t, s, N, _ in items})
+    line = {
+        "metric": "GB/s raw field (FWT+threshold+pack, and inverse)",
+        "value": res["plan"]["GBps"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["plan"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "24 mixed fields (edges 96..768, N 16/32/64, float32/float64, W4/W4_li/W3_ai), "
+                               "eps 1e-3 of range; captured batched plan",
+                   "raw_bytes_per_step": raw_total, "classes": len(classes), "tuned_entries": codec.tuned},
+        "single_field_launches": res["plain"],
+        "batch_call": res["batch"],
+        "captured_plan": res["plan"],
+        "speedup_plan_vs_single": round(res["plain"]["ms_per_step"] / res["plan"]["ms_per_step"], 3),
+        "identical_streams_and_fields": identical,
+        "cr_stage1": [round(t.numel() * t.element_size() / sp[i], 3) for i, (_, t, _, _, _) in enumerate(items)],
+    }
+    print(json.dumps(line), flush=True)
+    if not identical:
+        raise SystemExit("batched output differs from the single-field calls")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4"])
     ap.add_argument("--cpu-blocks", type=int, default=400, help="oracle sample: blocks per field")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-zlib", action="store_true", help="skip the host lossless stage and the C2 sweep")
@@ -175,6 +301,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU exchange is not built",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        return main_c4(args)
 
     import torch
 

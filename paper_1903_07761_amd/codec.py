@@ -18,11 +18,19 @@ def _stream_handle(device) -> int:
 
 
 class Codec:
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tuned: bool = True):
+        """tuned: select the kernel variants recorded for this device's
+        architecture by the autotuner, when a table exists (outputs do not
+        depend on the variant)."""
         if not torch.cuda.is_available():
             raise RuntimeError("the wavelet stage runs on a HIP device; none is available")
         self.device = torch.device("cuda", device)
         self.ctx = _cz.Context(device)
+        self.tuned = 0
+        if tuned:
+            from . import autotune
+
+            self.tuned = autotune.apply(self)
 
     def params(self, field: torch.Tensor, block: int, scheme, epsilon: float) -> _cz.cz_params:
         nz, ny, nx = field.shape

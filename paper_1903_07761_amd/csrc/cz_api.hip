@@ -136,6 +136,7 @@ struct cz_ctx {
     czk::CzWork *pinned = nullptr;  // host-pinned mirror for synchronous reads
     DevBuf flags;                   // plain calls: look-back flags
     DevBuf scratch;                 // plain calls on 64^3 blocks: one slot per resident workgroup
+    czk::FieldDesc *one = nullptr;  // device: the descriptor of a plain call (published by its prep kernel)
     uint8_t variant[4][2][3] = {};  // tuned kernel variant per (N, precision, scheme)
     BatchWork batch;                // batch calls
 };
@@ -513,6 +514,7 @@ int cz_create(cz_ctx **out, int device)
     ctx->device = device;
     const bool ok = hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
                     hipMalloc(&ctx->work, sizeof(czk::CzWork)) == hipSuccess &&
+                    hipMalloc(&ctx->one, sizeof(czk::FieldDesc)) == hipSuccess &&
                     hipMemset(ctx->work, 0, sizeof(czk::CzWork)) == hipSuccess &&
                     hipHostMalloc(&ctx->pinned, sizeof(czk::CzWork), hipHostMallocDefault) == hipSuccess &&
                     ctx->flags.ensure(4096 * sizeof(uint64_t)) == CZ_OK && ctx->batch.init() == CZ_OK;
@@ -535,6 +537,8 @@ void cz_destroy(cz_ctx *ctx)
     ctx->batch.release();
     if (ctx->work)
         (void)hipFree(ctx->work);
+    if (ctx->one)
+        (void)hipFree(ctx->one);
     if (ctx->pinned)
         (void)hipHostFree(ctx->pinned);
     delete ctx;
@@ -597,6 +601,7 @@ int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_ou
 
     czk::Queue q = work_queue(ctx);
     q.ntickets = nb;
+    q.fields = q.publish = ctx->one;
     q.one = describe(*p, nb, true);
     q.one.src = d_field;
     q.one.dst = d_out;
@@ -692,6 +697,7 @@ int cz_decompress(cz_ctx *ctx, const cz_params *expected, const void *d_in, size
         return CZ_ERR_ARG;
     czk::Queue q = work_queue(ctx);
     q.ntickets = nb;
+    q.fields = q.publish = ctx->one;
     q.one = describe(p, nb, false);
     q.one.src = d_in;
     q.one.dst = d_field;

@@ -43,15 +43,19 @@ struct FieldDesc {
 
 // A device work queue: tickets [0, ntickets) map, in order, onto the blocks
 // of the fields (field f owns tickets [first_f, first_f + nblocks_f)).  A
-// single-field queue carries its descriptor inline (fields == nullptr).
+// single-field call passes its descriptor inline (`one`) with `publish` ==
+// `fields` pointing at a device slot; its prep kernel copies the descriptor
+// there before the block kernel runs.
 struct Queue {
-    const FieldDesc *fields;
+    const FieldDesc *fields;  // the block kernels read every descriptor from here
     uint32_t nfields;
     uint32_t reserved;
     uint64_t ntickets;
     uint32_t *ticket;     // device ticket counter
     uint32_t *status;     // device STATUS_* bits
+    uint32_t *fstatus;    // optional: STATUS_* bits per field, indexed like fields
     void *scratch;        // N = 64: one N^3 slot of the field type per workgroup
+    FieldDesc *publish;   // optional: the prep kernel copies `one` here (a one-field table)
     FieldDesc one;
 };
 

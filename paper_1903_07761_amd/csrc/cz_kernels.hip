@@ -52,36 +52,58 @@ __device__ __forceinline__ void atomic_store_u64(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Decoupled look-back (single thread): publish this block's record size,
-// return the sum of the sizes of all earlier blocks.  Every wait is bounded;
-// on exhaustion the status word gets STATUS_TIMEOUT and 0 is returned.
-__device__ uint64_t lookback(uint64_t *flags, uint64_t b, uint64_t size, uint32_t *status)
+// Decoupled look-back over the blocks of a field, run by one wavefront:
+// publish this block's record size (FLAG_AGG), sum the sizes of the earlier
+// blocks back to the nearest inclusive prefix, publish the inclusive prefix
+// (FLAG_INC) and return the exclusive one (on every lane).  Lane k examines
+// the flag of the (k+1)-th nearest earlier block, so one step covers 64
+// predecessors; the lanes up to the nearest inclusive prefix must all have
+// published before their sizes are summed.  Every wait is bounded: on
+// exhaustion the status word gets STATUS_TIMEOUT.
+__device__ uint64_t lookback_wave(uint64_t *flags, uint64_t b, uint64_t size, uint32_t *status, uint32_t *fstatus)
 {
+    const uint32_t lane = __lane_id();
     if (b == 0) {
-        atomic_store_u64(&flags[0], FLAG_INC | size);
+        if (lane == 0)
+            atomic_store_u64(&flags[0], FLAG_INC | size);
         return 0;
     }
-    atomic_store_u64(&flags[b], FLAG_AGG | size);
+    if (lane == 0)
+        atomic_store_u64(&flags[b], FLAG_AGG | size);
     uint64_t excl = 0;
-    uint64_t j = b - 1;
+    uint64_t top = b;  // this step covers blocks [top - 64, top)
     uint32_t spins = 0;
     while (true) {
-        uint64_t f = atomic_load_u64(&flags[j]);
-        uint64_t st = f & ~FLAG_VAL;
-        if (st == 0) {
+        const bool valid = top > (uint64_t)lane;
+        const uint64_t f = valid ? atomic_load_u64(&flags[top - 1 - lane]) : FLAG_INC;
+        const uint64_t st = f & ~FLAG_VAL;
+        const uint64_t inc = __ballot(st == FLAG_INC);
+        const uint64_t empty = __ballot(st == 0);
+        const uint32_t first = inc ? (uint32_t)__builtin_ctzll(inc) : 64u;
+        const uint64_t upto = first >= 63 ? ~0ull : ((2ull << first) - 1ull);  // lanes [0, first]
+        if (empty & upto) {
             if (++spins > LOOKBACK_SPIN_LIMIT) {
-                atomicOr(status, STATUS_TIMEOUT);
+                if (lane == 0) {
+                    atomicOr(status, STATUS_TIMEOUT);
+                    if (fstatus)
+                        atomicOr(fstatus, STATUS_TIMEOUT);
+                }
                 break;
             }
             __builtin_amdgcn_s_sleep(2);
             continue;
         }
-        excl += f & FLAG_VAL;
-        if (st == FLAG_INC)
+        uint64_t v = lane <= first ? (f & FLAG_VAL) : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            v += __shfl_xor(v, o);
+        excl += v;
+        if (inc)
             break;
-        --j;
+        top -= 64;
     }
-    atomic_store_u64(&flags[b], FLAG_INC | (excl + size));
+    if (lane == 0)
+        atomic_store_u64(&flags[b], FLAG_INC | (excl + size));
     return excl;
 }
 
@@ -318,15 +340,27 @@ __device__ __forceinline__ void stage_lines(T *lds)
 
 // Decimation test |c| >= eps in double.  For float data this equals
 // |c| >= eps_f with eps_f the smallest float >= eps (computed on the host).
+// What a block kernel needs of its field (see field_view).
+struct FieldView {
+    const void *src;
+    void *dst;
+    uint64_t *flags;
+    uint64_t *total;
+    uint32_t nx, ny, nbx, nby;
+    uint64_t nblocks, p0, payload, first;
+    double eps;
+    float eps_f;
+};
+
 template <typename T>
-__device__ __forceinline__ bool keep_test(T v, const FieldDesc &a);
+__device__ __forceinline__ bool keep_test(T v, const FieldView &a);
 template <>
-__device__ __forceinline__ bool keep_test<float>(float v, const FieldDesc &a)
+__device__ __forceinline__ bool keep_test<float>(float v, const FieldView &a)
 {
     return __builtin_fabsf(v) >= a.eps_f;
 }
 template <>
-__device__ __forceinline__ bool keep_test<double>(double v, const FieldDesc &a)
+__device__ __forceinline__ bool keep_test<double>(double v, const FieldView &a)
 {
     return __builtin_fabs(v) >= a.eps;
 }
@@ -334,7 +368,7 @@ __device__ __forceinline__ bool keep_test<double>(double v, const FieldDesc &a)
 // Issue the loads of slab group g of block b: planes [g Z, g Z + Z), one
 // coalesced row segment per plane and column.
 template <typename T, int N, int Z, int R>
-__device__ __forceinline__ void load_planes(const FieldDesc &a, uint64_t b, int g, uint32_t lane_off, T (*dst)[N])
+__device__ __forceinline__ void load_planes(const FieldView &a, uint64_t b, int g, uint32_t lane_off, T (*dst)[N])
 {
     using G = Geom<T, N, Z, R>;
     const size_t plane = (size_t)a.nx * a.ny;
@@ -355,8 +389,6 @@ __device__ __forceinline__ void load_planes(const FieldDesc &a, uint64_t b, int 
 // The field that owns ticket t (fields hold consecutive ticket ranges).
 __device__ __forceinline__ uint32_t field_of_ticket(const Queue &q, uint64_t t)
 {
-    if (!q.fields)
-        return 0;
     uint32_t lo = 0, hi = q.nfields - 1;  // last field whose range starts at or before t
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
@@ -368,9 +400,53 @@ __device__ __forceinline__ uint32_t field_of_ticket(const Queue &q, uint64_t t)
     return lo;
 }
 
+// The descriptor of field f as the prep kernel sees it: a one-field queue
+// carries it inline until the prep kernel publishes it to q.fields.
 __device__ __forceinline__ const FieldDesc &field_desc(const Queue &q, uint32_t f)
 {
-    return q.fields ? q.fields[f] : q.one;
+    return q.publish ? q.one : q.fields[f];
+}
+
+// The per-field values the block kernels read.  The field index is made
+// wave-uniform first, so the descriptor is fetched from the table with scalar
+// loads into SGPRs instead of occupying VGPRs for the whole block.  (One
+// source only: choosing between two descriptor sources costs SGPRs for the
+// whole kernel and measurably slows the forward transform.)
+__device__ __forceinline__ FieldView view_of(const FieldDesc &d)
+{
+    return FieldView{d.src, d.dst, d.flags, d.total, d.nx, d.ny, d.nbx, d.nby, d.nblocks, d.p0, d.payload, d.first,
+                     d.eps, d.eps_f};
+}
+
+// The table is read through the constant address space: it is written before
+// the launch (host copy or the prep kernel) and never during it, and only
+// loads from that space become scalar loads through the scalar cache; a
+// generic pointer would make them vector loads, each a full memory round trip
+// on the path to the block's first load.
+using ConstDesc = const __attribute__((address_space(4))) FieldDesc;
+
+__device__ __forceinline__ FieldView field_view(const Queue &q, uint32_t f)
+{
+    f = __builtin_amdgcn_readfirstlane(f);
+    ConstDesc *d = (ConstDesc *)q.fields + f;
+    return FieldView{d->src, d->dst, d->flags, d->total, d->nx, d->ny, d->nbx, d->nby, d->nblocks, d->p0,
+                     d->payload, d->first, d->eps, d->eps_f};
+}
+
+// Latch STATUS_* bits for the queue and, when per-field words exist, for
+// field f.
+__device__ __forceinline__ void report(const Queue &q, uint32_t f, uint32_t bits)
+{
+    atomicOr(q.status, bits);
+    if (q.fstatus)
+        atomicOr(q.fstatus + f, bits);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // One workgroup per block: the block's ticket is taken at workgroup start,
@@ -398,10 +474,10 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
         s_field = t < q.ntickets ? field_of_ticket(q, t) : 0u;
     }
     lds_barrier();
-    const uint64_t t = s_block;
+    const uint64_t t = uniform64(s_block);
     if (t >= q.ntickets)
         return;
-    const FieldDesc &a = field_desc(q, s_field);
+    const FieldView a = field_view(q, s_field);
     const uint64_t b = t - a.first;
     const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;  // element offset of (x, yq) in a z-plane
 
@@ -501,7 +577,7 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
         keepbits[r] = kb;
     }
     if (bad)
-        atomicOr(q.status, STATUS_NONFINITE);
+        report(q, s_field, STATUS_NONFINITE);
     // mask words: lane z R + r of each wavefront keeps the ballot of (z, r)
     uint64_t myword = 0;
 #pragma unroll
@@ -526,8 +602,11 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
 
     const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
     const uint64_t rbytes = (used + 15ull) & ~15ull;
-    if (tid == 0)
-        s_off = lookback(a.flags, b, rbytes, q.status);
+    if (tid < 64) {
+        const uint64_t o = lookback_wave(a.flags, b, rbytes, q.status, q.fstatus ? q.fstatus + s_field : nullptr);
+        if (tid == 0)
+            s_off = o;
+    }
     lds_barrier();
     const uint64_t off = s_off;
     uint8_t *out = static_cast<uint8_t *>(a.dst);
@@ -597,7 +676,7 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
             uint32_t ok = 0, f = 0;
             if (t < q.ntickets) {
                 f = field_of_ticket(q, t);
-                const FieldDesc &a = field_desc(q, f);
+                const FieldView a = field_view(q, f);
                 const uint8_t *in = static_cast<const uint8_t *>(a.src);
                 const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
                 const uint64_t b = t - a.first;
@@ -609,21 +688,21 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
                     ok = nnz <= (uint32_t)(N * N * N) && ((used + 15ull) & ~15ull) == o1 - o0;
                 }
                 if (!ok)
-                    atomicOr(q.status, STATUS_FORMAT);
+                    report(q, f, STATUS_FORMAT);
             }
             s_block = t;
             s_field = f;
             s_ok = ok;
         }
         lds_barrier();
-        const uint64_t t = s_block;
+        const uint64_t t = uniform64(s_block);
         if (t >= q.ntickets)
             break;
         if (!s_ok) {
             lds_barrier();
             continue;
         }
-        const FieldDesc &a = field_desc(q, s_field);
+        const FieldView a = field_view(q, s_field);
         const uint64_t b = t - a.first;
         const size_t plane = (size_t)a.nx * a.ny;
         const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;
@@ -645,7 +724,7 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
         lds_barrier();
         if (s_scan[G::WAVES] != nnz) {
             if (tid == 0)
-                atomicOr(q.status, STATUS_FORMAT);
+                report(q, s_field, STATUS_FORMAT);
             lds_barrier();
             continue;
         }
@@ -843,10 +922,10 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
             s_bad = 0;
         }
         gbarrier<NT>();
-        const uint64_t t = s_block;
+        const uint64_t t = uniform64(s_block);
         if (t >= q.ntickets)
             break;
-        const FieldDesc &a = field_desc(q, s_field);
+        const FieldView a = field_view(q, s_field);
         const uint64_t b = t - a.first;
         const size_t plane = (size_t)a.nx * a.ny;
         const uint32_t bx = (uint32_t)(b % a.nbx);
@@ -878,12 +957,15 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
             s_bad = 1;
         gbarrier<NT>();
         if (tid == 0 && s_bad)
-            atomicOr(q.status, STATUS_NONFINITE);
+            report(q, s_field, STATUS_NONFINITE);
         const uint32_t nnz = scan_words<NT, WORDS>(s_words, s_pre, s_scan);
         const uint64_t used = 8ull + MASK_BYTES + (uint64_t)nnz * sizeof(T);
         const uint64_t rbytes = (used + 15ull) & ~15ull;
-        if (tid == 0)
-            s_off = lookback(a.flags, b, rbytes, q.status);
+        if (tid < 64) {
+            const uint64_t o = lookback_wave(a.flags, b, rbytes, q.status, q.fstatus ? q.fstatus + s_field : nullptr);
+            if (tid == 0)
+                s_off = o;
+        }
         gbarrier<NT>();
         const uint64_t off = s_off;
         uint8_t *out = static_cast<uint8_t *>(a.dst);
@@ -938,7 +1020,7 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
             uint32_t ok = 0, f = 0;
             if (t < q.ntickets) {
                 f = field_of_ticket(q, t);
-                const FieldDesc &a = field_desc(q, f);
+                const FieldView a = field_view(q, f);
                 const uint8_t *in = static_cast<const uint8_t *>(a.src);
                 const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
                 const uint64_t b = t - a.first;
@@ -950,21 +1032,21 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
                     ok = nnz <= (uint32_t)(N * N * N) && ((used + 15ull) & ~15ull) == o1 - o0;
                 }
                 if (!ok)
-                    atomicOr(q.status, STATUS_FORMAT);
+                    report(q, f, STATUS_FORMAT);
             }
             s_block = t;
             s_field = f;
             s_ok = ok;
         }
         gbarrier<NT>();
-        const uint64_t t = s_block;
+        const uint64_t t = uniform64(s_block);
         if (t >= q.ntickets)
             break;
         if (!s_ok) {
             gbarrier<NT>();
             continue;
         }
-        const FieldDesc &a = field_desc(q, s_field);
+        const FieldView a = field_view(q, s_field);
         const uint64_t b = t - a.first;
         const size_t plane = (size_t)a.nx * a.ny;
         const uint8_t *in = static_cast<const uint8_t *>(a.src);
@@ -980,7 +1062,7 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
         gbarrier<NT>();
         if (total != nnz) {
             if (tid == 0)
-                atomicOr(q.status, STATUS_FORMAT);
+                report(q, s_field, STATUS_FORMAT);
             gbarrier<NT>();
             continue;
         }
@@ -1007,7 +1089,8 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
 
 // ------------------------------------------------------------- bookkeeping
 
-// Reset the queue's ticket and status.  Forward: for every field (y index
+// Reset the queue's ticket and status and publish an inline descriptor.
+// Forward: for every field (y index
 // of the grid) clear its look-back flags and write its header (payload size
 // 0 until its last block fills it), offset 0 and the zero pad between its
 // offset table and payload; a field without blocks gets its total here.
@@ -1018,6 +1101,8 @@ __global__ void prep_kernel(Queue q, int forward)
     if (i0 == 0 && blockIdx.y == 0) {
         *q.ticket = 0;
         *q.status = 0;
+        if (q.publish)
+            *q.publish = q.one;
     }
     if (!forward)
         return;
