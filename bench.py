@@ -249,6 +249,23 @@ def main_c4(args):
         log(f"c4 {name}: {ms:.3f} ms per step")
     plan_sizes = plan_c.result(stream=sh)
 
+    # per-field single-launch timing (forward, inverse), for the breakdown
+    per_field = []
+    for i, (lab, t, s, N, e) in enumerate(items):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(st)
+        codec.compress(t, N, s, e, out=bufs["plain"][i], sync=False, out_bytes=sizes["plain"][i:i + 1])
+        ev[1].record(st)
+        codec.decompress(bufs["plain"][i], caps[i], out=recs["plain"][i], expected=ps[i])
+        ev[2].record(st)
+        torch.cuda.synchronize()
+        raw = t.numel() * t.element_size()
+        tf, ti = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+        per_field.append({"edge": t.shape[0], "dtype": str(t.dtype).replace("torch.", ""), "N": N, "scheme": s,
+                          "fwd_ms": round(tf, 3), "inv_ms": round(ti, 3),
+                          "fwd_GBps": round(raw / tf / 1e6, 1), "inv_GBps": round(raw / ti / 1e6, 1)})
+        log(f"c4 {lab}: {per_field[-1]}")
+
     log("c4 identity check")
     sp, sb = sizes["plain"].cpu().tolist(), sizes["batch"].cpu().tolist()
     identical = sp == sb == plan_sizes
@@ -280,6 +297,7 @@ def main_c4(args):
         "captured_plan": res["plan"],
         "speedup_plan_vs_single": round(res["plain"]["ms_per_step"] / res["plan"]["ms_per_step"], 3),
         "identical_streams_and_fields": identical,
+        "per_field_single_launch": per_field,
         "cr_stage1": [round(t.numel() * t.element_size() / sp[i], 3) for i, (_, t, _, _, _) in enumerate(items)],
     }
     print(json.dumps(line), flush=True)

@@ -341,6 +341,9 @@ int grid_for(const cz_ctx *ctx, const czk::KernelKey &key, bool inverse, uint64_
     if (per_cu < 1)
         per_cu = 1;
     uint64_t g = (uint64_t)per_cu * (uint64_t)ctx->num_cu;
+    const int cap = czk::grid_cap(key);
+    if (cap > 0 && g > (uint64_t)cap)
+        g = (uint64_t)cap;
     if (g > tickets)
         g = tickets;
     return (int)(g ? g : 1);

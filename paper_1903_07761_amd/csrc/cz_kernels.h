@@ -79,5 +79,7 @@ int occupancy(const KernelKey &key, bool inverse);
 bool fwd_one_block_per_workgroup(const KernelKey &key);
 // Number of compiled shape variants for (block, elem_bytes).
 int variant_count(uint32_t block, uint32_t elem_bytes);
+// Upper bound on the workgroups of a launch (0: none).
+int grid_cap(const KernelKey &key);
 
 }  // namespace czk

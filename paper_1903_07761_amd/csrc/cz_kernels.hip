@@ -1281,10 +1281,18 @@ int occupancy(const KernelKey &key, bool inverse)
 
 bool fwd_one_block_per_workgroup(const KernelKey &key) { return key.block <= 32; }
 
+// 64^3 variants differ only in how many workgroups (each with its scratch
+// slot) are resident at once: 256, 128 or 64.  Fewer slots keep the scratch
+// working set in the last-level cache at the price of idle CUs.
 int variant_count(uint32_t block, uint32_t elem_bytes)
 {
     (void)elem_bytes;
-    return (block == 16 || block == 32) ? 2 : 1;
+    return (block == 16 || block == 32) ? 2 : block == 64 ? 3 : 1;
+}
+
+int grid_cap(const KernelKey &key)
+{
+    return key.block == 64 ? 256 >> (key.variant < 3 ? key.variant : 0) : 0;
 }
 
 hipError_t launch_fold_status(const uint32_t *counters, int nclass, uint32_t *status, hipStream_t st)
