@@ -196,6 +196,60 @@ int cz_plan_run(cz_plan *plan, const void *const *srcs, const size_t *src_bytes,
 int cz_plan_result(cz_plan *plan, void *stream, size_t *h_out_bytes);
 void cz_plan_destroy(cz_plan *plan);
 
+/* ------------------------------------------------------------------ serving
+ *
+ * A scheduler for a stream of independent requests (the in-situ use of
+ * Sec. 1-2: each quantity is handed over as the simulation produces it).  A
+ * worker thread admits requests from an arrival FIFO, strictly in order, while
+ * the admitted-but-unfinished requests number at most max_inflight and their
+ * device footprint (compress: raw field + cz_compress_bound; decompress:
+ * src_bytes + raw field) stays within hbm_budget_bytes, and launches whatever
+ * it admitted at once as one batch (grouped by kernel class as in
+ * cz_compress_batch), with up to four batches in flight.  Outputs are
+ * byte-identical to the single-field calls.
+ *
+ * The caller owns every buffer; a request's source must be complete (its
+ * producing stream synchronised) before cz_submit, and its buffers must stay
+ * valid until it is done.  The server keeps its own device workspace; the
+ * context's variant table must not change while the server runs.  Times are
+ * seconds on the server's monotonic clock (cz_server_time), from its start. */
+typedef struct cz_server cz_server;
+
+typedef struct {
+    int op;              /* 0 = compress, 1 = decompress                        */
+    cz_params p;         /* decompress: the parameters the stream was made with */
+    const void *d_src;   /* compress: the field; decompress: the stream         */
+    size_t src_bytes;    /* decompress: stream size (ignored for compress)      */
+    void *d_dst;         /* compress: stream buffer; decompress: the field      */
+    size_t dst_cap;      /* capacity of d_dst in bytes                          */
+    uint64_t user_tag;   /* returned untouched                                  */
+} cz_request;
+
+/* Start a server on ctx's device.  CZ_ERR_ARG for max_inflight < 1 or a zero
+ * budget. */
+int cz_server_start(cz_ctx *ctx, size_t hbm_budget_bytes, int max_inflight, cz_server **out);
+
+/* Queue a request (non-blocking).  Validation errors (CZ_ERR_ARG, _SHAPE,
+ * _CAPACITY, _FORMAT) and CZ_ERR_BUDGET (footprint above the budget) are
+ * returned at once and nothing is queued; otherwise *ticket identifies it. */
+int cz_submit(cz_server *s, const cz_request *r, uint64_t *ticket);
+
+/* State of a request: *done = 1 once finished, with its CZ_* status, the
+ * stream size (compress) and its arrival, admission and completion times
+ * (-1 until they happen).  Any output pointer but done may be NULL. */
+int cz_poll(cz_server *s, uint64_t ticket, int *done, int *status, size_t *out_bytes, double *t_arrive,
+            double *t_admit, double *t_done);
+
+/* Block until the request is done; returns its status. */
+int cz_wait(cz_server *s, uint64_t ticket);
+
+/* Seconds since the server started, on the clock of cz_poll's times. */
+double cz_server_time(cz_server *s);
+
+/* Finish every queued request, stop the worker and free the server.
+ * Returns CZ_ERR_HIP if the device failed while serving, else CZ_OK. */
+int cz_server_stop(cz_server *s);
+
 #ifdef __cplusplus
 }
 #endif

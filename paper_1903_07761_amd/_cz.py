@@ -26,6 +26,11 @@ class cz_params(ctypes.Structure):
                 ("epsilon", ctypes.c_double)]
 
 
+class cz_request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("p", cz_params), ("d_src", ctypes.c_void_p), ("src_bytes", ctypes.c_size_t),
+                ("d_dst", ctypes.c_void_p), ("dst_cap", ctypes.c_size_t), ("user_tag", ctypes.c_uint64)]
+
+
 class CzError(RuntimeError):
     def __init__(self, code: int, what: str, detail: str = ""):
         super().__init__(f"{what}: {strerror(code)} ({code}){' ' + detail if detail else ''}")
@@ -79,6 +84,19 @@ def lib() -> ctypes.CDLL:
         L.cz_plan_result.restype = i32
         L.cz_plan_destroy.argtypes = [vp]
         L.cz_plan_destroy.restype = None
+        L.cz_server_start.argtypes = [vp, sz, i32, PP]
+        L.cz_server_start.restype = i32
+        L.cz_submit.argtypes = [vp, ctypes.POINTER(cz_request), ctypes.POINTER(u64)]
+        L.cz_submit.restype = i32
+        pd = ctypes.POINTER(ctypes.c_double)
+        L.cz_poll.argtypes = [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(i32), PS, pd, pd, pd]
+        L.cz_poll.restype = i32
+        L.cz_wait.argtypes = [vp, u64]
+        L.cz_wait.restype = i32
+        L.cz_server_time.argtypes = [vp]
+        L.cz_server_time.restype = ctypes.c_double
+        L.cz_server_stop.argtypes = [vp]
+        L.cz_server_stop.restype = i32
         _lib = L
     return _lib
 
@@ -233,3 +251,49 @@ def read_header(hdr: bytes):
     nb, tot = ctypes.c_uint64(0), ctypes.c_uint64(0)
     _check(lib().cz_read_header(buf, 64, ctypes.byref(p), ctypes.byref(nb), ctypes.byref(tot)), "cz_read_header")
     return p, nb.value, tot.value
+
+
+class Server:
+    """A libcz serving scheduler (continuous batching under a memory budget)."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_inflight: int):
+        h = ctypes.c_void_p()
+        _check(lib().cz_server_start(ctx.handle, int(budget_bytes), int(max_inflight), ctypes.byref(h)),
+               "cz_server_start")
+        self.handle = h
+        self.ctx = ctx
+
+    def submit(self, op: int, p: cz_params, d_src: int, src_bytes: int, d_dst: int, dst_cap: int,
+               tag: int = 0) -> int:
+        r = cz_request(op, p, d_src, src_bytes, d_dst, dst_cap, tag)
+        t = ctypes.c_uint64(0)
+        _check(lib().cz_submit(self.handle, ctypes.byref(r), ctypes.byref(t)), "cz_submit")
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        done, st = ctypes.c_int(0), ctypes.c_int(0)
+        nb = ctypes.c_size_t(0)
+        ta, tb, tc = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        _check(lib().cz_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(nb),
+                             ctypes.byref(ta), ctypes.byref(tb), ctypes.byref(tc)), "cz_poll")
+        return {"done": bool(done.value), "status": st.value, "out_bytes": nb.value, "t_arrive": ta.value,
+                "t_admit": tb.value, "t_done": tc.value}
+
+    def wait(self, ticket: int) -> int:
+        return int(lib().cz_wait(self.handle, ticket))
+
+    def time(self) -> float:
+        return float(lib().cz_server_time(self.handle))
+
+    def stop(self) -> int:
+        rc = OK
+        if self.handle:
+            rc = int(lib().cz_server_stop(self.handle))
+            self.handle = None
+        return rc
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

@@ -15,153 +15,9 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/cz.h"
-#include "cz_kernels.h"
+#include "cz_host.h"
 
-namespace {
-
-constexpr uint32_t MAGIC = 0x31425A43u;  // "CZB1" little-endian
-constexpr uint64_t MAX_BLOCKS = 1ull << 31;
-constexpr uint64_t HDR = 64;
-constexpr int MAX_CLASSES = 24;  // 4 block sizes x 2 precisions x 3 schemes
-
-// Device memory that grows on demand (freed with its owner).
-struct DevBuf {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-    int ensure(size_t want)
-    {
-        if (want <= bytes)
-            return CZ_OK;
-        void *fresh = nullptr;
-        if (hipMalloc(&fresh, want) != hipSuccess)
-            return CZ_ERR_HIP;
-        if (ptr) {
-            (void)hipDeviceSynchronize();  // earlier work may still use the old buffer
-            (void)hipFree(ptr);
-        }
-        ptr = fresh;
-        bytes = want;
-        return CZ_OK;
-    }
-    void release()
-    {
-        if (ptr)
-            (void)hipFree(ptr);
-        ptr = nullptr;
-        bytes = 0;
-    }
-};
-
-// Workspace of a batch: the device descriptor table and its pinned staging,
-// look-back flags, per-class (ticket, status) counters, stream sizes, 64^3
-// scratch, and the lanes the classes run on concurrently.
-struct BatchWork {
-    DevBuf desc, flags, counters, totals, scratch;
-    czk::FieldDesc *stage = nullptr;  // pinned, uploaded in stream order
-    uint64_t *totals_host = nullptr;  // pinned readback of stream sizes
-    size_t cap = 0;                   // fields the pinned buffers hold
-    hipEvent_t staged = nullptr;      // the staging may be rewritten once this fired
-    hipStream_t lanes[MAX_CLASSES] = {};
-    hipEvent_t fork = nullptr, joins[MAX_CLASSES] = {};
-
-    int init()
-    {
-        if (hipEventCreateWithFlags(&staged, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventRecord(staged, nullptr) != hipSuccess)
-            return CZ_ERR_HIP;
-        return CZ_OK;
-    }
-    // Streams (default priority) and join events for the first n lanes.
-    int lanes_for(size_t n)
-    {
-        for (size_t i = 0; i < n && i < (size_t)MAX_CLASSES; ++i) {
-            if (!lanes[i] && hipStreamCreateWithFlags(&lanes[i], hipStreamNonBlocking) != hipSuccess)
-                return CZ_ERR_HIP;
-            if (!joins[i] && hipEventCreateWithFlags(&joins[i], hipEventDisableTiming) != hipSuccess)
-                return CZ_ERR_HIP;
-        }
-        return CZ_OK;
-    }
-    int pinned(size_t n)
-    {
-        if (n <= cap)
-            return CZ_OK;
-        if (staged)
-            (void)hipEventSynchronize(staged);
-        if (stage)
-            (void)hipHostFree(stage);
-        if (totals_host)
-            (void)hipHostFree(totals_host);
-        stage = nullptr;
-        totals_host = nullptr;
-        cap = 0;
-        if (hipHostMalloc(&stage, n * sizeof(czk::FieldDesc), hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc(&totals_host, n * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
-            return CZ_ERR_HIP;
-        cap = n;
-        return CZ_OK;
-    }
-    void release()
-    {
-        desc.release();
-        flags.release();
-        counters.release();
-        totals.release();
-        scratch.release();
-        if (stage)
-            (void)hipHostFree(stage);
-        if (totals_host)
-            (void)hipHostFree(totals_host);
-        if (staged)
-            (void)hipEventDestroy(staged);
-        if (fork)
-            (void)hipEventDestroy(fork);
-        for (int i = 0; i < MAX_CLASSES; ++i) {
-            if (lanes[i])
-                (void)hipStreamDestroy(lanes[i]);
-            if (joins[i])
-                (void)hipEventDestroy(joins[i]);
-        }
-    }
-};
-
-}  // namespace
-
-struct cz_ctx {
-    int device = 0;
-    int num_cu = 0;
-    czk::CzWork *work = nullptr;    // device: ticket, status, total of plain calls
-    czk::CzWork *pinned = nullptr;  // host-pinned mirror for synchronous reads
-    DevBuf flags;                   // plain calls: look-back flags
-    DevBuf scratch;                 // plain calls on 64^3 blocks: one slot per resident workgroup
-    czk::FieldDesc *one = nullptr;  // device: the descriptor of a plain call (published by its prep kernel)
-    uint8_t variant[4][2][3] = {};  // tuned kernel variant per (N, precision, scheme)
-    BatchWork batch;                // batch calls
-};
-
-namespace {
-
-// Class of a field: fields of one class share a kernel and one queue.
-using ClassKey = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>;
-
-struct Layout {
-    bool forward = true;
-    int n = 0;
-    std::vector<uint64_t> nblocks;      // per field
-    std::vector<int> order;             // field indices grouped by class
-    std::vector<czk::KernelKey> keys;   // per class
-    std::vector<uint32_t> first, count; // per class: its range in `order`
-    std::vector<uint64_t> tickets;      // per class
-    std::vector<int> grids;             // per class
-    std::vector<size_t> scratch_off;    // per class: its 64^3 slots
-    size_t scratch_bytes = 0;
-    std::vector<uint64_t> flag_base;    // per field (forward): offset into the flags
-    uint64_t flags_total = 0;
-};
-
-}  // namespace
+using namespace czh;
 
 struct cz_plan {
     cz_ctx *ctx = nullptr;
@@ -173,24 +29,7 @@ struct cz_plan {
     hipEvent_t done = nullptr;  // the last run has finished with the staging
 };
 
-namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess)
-            prev = -1;
-        if (prev != dev)
-            (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
-            (void)hipSetDevice(prev);
-    }
-};
+namespace czh {
 
 uint64_t roundup16(uint64_t v) { return (v + 15u) & ~uint64_t(15); }
 
@@ -401,6 +240,7 @@ int size_work(BatchWork &w, const Layout &L)
         (rc = w.flags.ensure(std::max<uint64_t>(L.flags_total, 1) * sizeof(uint64_t))) != CZ_OK ||
         (rc = w.counters.ensure(2 * MAX_CLASSES * sizeof(uint32_t))) != CZ_OK ||
         (rc = w.totals.ensure(std::max(L.n, 1) * sizeof(uint64_t))) != CZ_OK ||
+        (rc = w.fstat.ensure(std::max(L.n, 1) * sizeof(uint32_t))) != CZ_OK ||
         (rc = w.scratch.ensure(std::max<size_t>(L.scratch_bytes, 1))) != CZ_OK || (rc = w.pinned(L.n)) != CZ_OK ||
         (rc = w.lanes_for(L.keys.size())) != CZ_OK)
         return rc;
@@ -436,7 +276,7 @@ void stage_batch(BatchWork &w, const Layout &L, const cz_params *ps, const void 
 // Enqueue a staged batch on st: upload the descriptors, then every class on
 // its own lane (forked from st, joined back), then fold the class status
 // words into *status and copy the stream sizes to pinned memory.
-int enqueue_batch(BatchWork &w, const Layout &L, uint32_t *status, hipStream_t st)
+int enqueue_batch(BatchWork &w, const Layout &L, uint32_t *status, bool per_field, hipStream_t st)
 {
     czk::FieldDesc *desc = static_cast<czk::FieldDesc *>(w.desc.ptr);
     uint32_t *counters = static_cast<uint32_t *>(w.counters.ptr);
@@ -453,6 +293,7 @@ int enqueue_batch(BatchWork &w, const Layout &L, uint32_t *status, hipStream_t s
         q.ntickets = L.tickets[c];
         q.ticket = counters + 2 * c;
         q.status = counters + 2 * c + 1;
+        q.fstatus = static_cast<uint32_t *>(w.fstat.ptr) + L.first[c];
         q.scratch = static_cast<uint8_t *>(w.scratch.ptr) + L.scratch_off[c];
         if (czk::launch_prep(q, L.forward, lane) != hipSuccess)
             return CZ_ERR_HIP;
@@ -465,7 +306,10 @@ int enqueue_batch(BatchWork &w, const Layout &L, uint32_t *status, hipStream_t s
         if (hipEventRecord(w.joins[c], lane) != hipSuccess || hipStreamWaitEvent(st, w.joins[c], 0) != hipSuccess)
             return CZ_ERR_HIP;
     }
-    if (czk::launch_fold_status(counters, (int)L.keys.size(), status, st) != hipSuccess)
+    if (status && czk::launch_fold_status(counters, (int)L.keys.size(), status, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    if (per_field && hipMemcpyAsync(w.fstat_host, w.fstat.ptr, L.n * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                    st) != hipSuccess)
         return CZ_ERR_HIP;
     if (L.forward &&
         hipMemcpyAsync(w.totals_host, w.totals.ptr, L.n * sizeof(uint64_t), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -779,7 +623,7 @@ static int run_batch(cz_ctx *ctx, bool forward, int n, const cz_params *ps, cons
     if (hipEventSynchronize(w.staged) != hipSuccess)  // the previous upload has left the staging
         return CZ_ERR_HIP;
     stage_batch(w, L, ps, srcs, src_bytes, dsts);
-    if ((rc = enqueue_batch(w, L, &ctx->work->status, st)) != CZ_OK)
+    if ((rc = enqueue_batch(w, L, &ctx->work->status, false, st)) != CZ_OK)
         return rc;
     if (hipEventRecord(w.staged, st) != hipSuccess)
         return CZ_ERR_HIP;
@@ -860,7 +704,7 @@ int cz_plan_run(cz_plan *plan, const void *const *srcs, const size_t *src_bytes,
         if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
             rc = CZ_ERR_HIP;
         if (rc == CZ_OK)
-            rc = enqueue_batch(plan->work, L, &plan->ctx->work->status, cap);
+            rc = enqueue_batch(plan->work, L, &plan->ctx->work->status, false, cap);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(cap, &g);
         if (rc == CZ_OK && e != hipSuccess)

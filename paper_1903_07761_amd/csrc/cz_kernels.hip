@@ -1104,6 +1104,8 @@ __global__ void prep_kernel(Queue q, int forward)
         if (q.publish)
             *q.publish = q.one;
     }
+    if (i0 == 0 && q.fstatus)
+        q.fstatus[blockIdx.y] = 0;
     if (!forward)
         return;
     const FieldDesc &a = field_desc(q, blockIdx.y);
@@ -1308,7 +1310,8 @@ hipError_t launch_prep(const Queue &q, bool forward, hipStream_t st)
     int gx = (int)((most + 255) / 256);
     if (gx > 1024)
         gx = 1024;
-    hipLaunchKernelGGL(prep_kernel, dim3(gx, forward ? q.nfields : 1), dim3(256), 0, st, q, forward ? 1 : 0);
+    const uint32_t gy = forward || q.fstatus ? q.nfields : 1;
+    hipLaunchKernelGGL(prep_kernel, dim3(gx, gy), dim3(256), 0, st, q, forward ? 1 : 0);
     return hipGetLastError();
 }
 

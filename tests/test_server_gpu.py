@@ -1,0 +1,174 @@
+"""Serving scheduler: continuous batching under a device-memory budget.
+
+Every request is an independent compression problem, so each served output
+must be byte-identical to the single-field call with the same parameters
+(which the parity tests hold to the oracle).  Also checked: admission order
+and the budget / in-flight limits through the recorded times, error
+isolation between requests of one batch, and the submit-time rejections.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+TDT = {4: torch.float32, 8: torch.float64}
+
+
+@pytest.fixture(scope="module")
+def codec():
+    need_gpu()
+    from paper_1903_07761_amd.codec import Codec
+
+    return Codec(0)
+
+
+def request_mix(seed: int, count: int):
+    from paper_1903_07761_amd import fields
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        N = int(rng.choice([8, 16, 32, 64]))
+        edge = N * int(rng.integers(1, 4)) if N < 64 else 64
+        shape = (edge, N * int(rng.integers(1, 3)), edge)
+        elem = int(rng.choice([4, 8]))
+        s = ["W4", "W4_li", "W3_ai"][int(rng.integers(0, 3))]
+        n = max(shape)
+        f = fields.bubble_cloud(n, seed * 100 + i, nbubbles=10, dtype=TDT[elem])[: shape[0], : shape[1], : shape[2]]
+        f = f.contiguous().cuda()
+        eps = float(rng.choice([0.0, 1e-3, 1e-2])) * float(f.max() - f.min())
+        out.append((f, N, s, eps))
+    return out
+
+
+def test_served_outputs_match_single_calls(codec):
+    from paper_1903_07761_amd import _cz
+
+    items = request_mix(11, 24)
+    ref_streams, ref_fields = [], []
+    for f, N, s, eps in items:
+        buf, n = codec.compress(f, N, s, eps)
+        ref_streams.append(buf[:n].clone())
+        ref_fields.append(codec.decompress(buf, n))
+    torch.cuda.synchronize()
+    srv = _cz.Server(codec.ctx, 200e9, 64)
+    tickets = []
+    outs, recs = [], []
+    for k, (f, N, s, eps) in enumerate(items):
+        p = codec.params(f, N, s, eps)
+        # compress request, then a decompress request of the reference stream
+        o = torch.empty(_cz.compress_bound(p), dtype=torch.uint8, device="cuda")
+        r = torch.empty_like(f)
+        outs.append(o)
+        recs.append(r)
+        tickets.append(srv.submit(0, p, f.data_ptr(), 0, o.data_ptr(), o.numel(), tag=k))
+        tickets.append(srv.submit(1, p, ref_streams[k].data_ptr(), ref_streams[k].numel(), r.data_ptr(),
+                                  r.numel() * r.element_size(), tag=k))
+    for t in tickets:
+        assert srv.wait(t) == 0
+    info = [srv.poll(t) for t in tickets]
+    assert srv.stop() == 0
+    for k in range(len(items)):
+        ic, idc = info[2 * k], info[2 * k + 1]
+        n = ref_streams[k].numel()
+        assert ic["out_bytes"] == n, k
+        assert torch.equal(outs[k][:n], ref_streams[k]), k
+        assert recs[k].cpu().numpy().tobytes() == ref_fields[k].cpu().numpy().tobytes(), k
+        for d in (ic, idc):
+            assert d["done"] and d["status"] == 0
+            assert 0 <= d["t_arrive"] <= d["t_admit"] <= d["t_done"]
+    admits = [d["t_admit"] for d in info]
+    assert admits == sorted(admits), "admission must follow arrival order"
+    say(f"[serve] {len(tickets)} requests, last done at {max(d['t_done'] for d in info):.4f} s")
+
+
+def test_budget_and_inflight_limits(codec):
+    from paper_1903_07761_amd import _cz, fields
+
+    f = fields.gaussian_bumps(64, 5, dtype=torch.float32).cuda()
+    p = codec.params(f, 32, "W4", 1e-3)
+    bound = _cz.compress_bound(p)
+    foot = f.numel() * 4 + bound
+    outs = [torch.empty(bound, dtype=torch.uint8, device="cuda") for _ in range(6)]
+    # a budget that holds one request at a time serialises them
+    srv = _cz.Server(codec.ctx, foot + foot // 2, 64)
+    ts = [srv.submit(0, p, f.data_ptr(), 0, o.data_ptr(), o.numel()) for o in outs]
+    for t in ts:
+        assert srv.wait(t) == 0
+    info = [srv.poll(t) for t in ts]
+    assert srv.stop() == 0
+    for a, b in zip(info, info[1:]):
+        assert b["t_admit"] >= a["t_done"], "budget admitted two requests at once"
+    # max_inflight = 1 serialises as well
+    srv = _cz.Server(codec.ctx, 200e9, 1)
+    ts = [srv.submit(0, p, f.data_ptr(), 0, o.data_ptr(), o.numel()) for o in outs]
+    for t in ts:
+        assert srv.wait(t) == 0
+    info = [srv.poll(t) for t in ts]
+    assert srv.stop() == 0
+    for a, b in zip(info, info[1:]):
+        assert b["t_admit"] >= a["t_done"]
+    ref, n = codec.compress(f, 32, "W4", 1e-3)
+    for o, d in zip(outs, info):
+        assert d["out_bytes"] == n and torch.equal(o[:n], ref[:n])
+
+
+def test_submit_rejections(codec):
+    from paper_1903_07761_amd import _cz
+
+    f = torch.zeros((32, 32, 32), dtype=torch.float32, device="cuda")
+    p = codec.params(f, 32, "W4", 0.0)
+    bound = _cz.compress_bound(p)
+    o = torch.empty(bound, dtype=torch.uint8, device="cuda")
+    srv = _cz.Server(codec.ctx, f.numel() * 4 + bound - 1, 4)
+    with pytest.raises(_cz.CzError) as e:
+        srv.submit(0, p, f.data_ptr(), 0, o.data_ptr(), o.numel())
+    assert e.value.code == _cz.ERR_BUDGET
+    srv.stop()
+    srv = _cz.Server(codec.ctx, 1e9, 4)
+    with pytest.raises(_cz.CzError) as e:
+        srv.submit(0, p, f.data_ptr(), 0, o.data_ptr(), bound - 16)
+    assert e.value.code == _cz.ERR_CAPACITY
+    bad = codec.params(f, 24, "W4", 0.0)
+    with pytest.raises(_cz.CzError) as e:
+        srv.submit(0, bad, f.data_ptr(), 0, o.data_ptr(), o.numel())
+    assert e.value.code == _cz.ERR_SHAPE
+    with pytest.raises(_cz.CzError) as e:
+        srv.submit(1, p, o.data_ptr(), 32, f.data_ptr(), f.numel() * 4)
+    assert e.value.code == _cz.ERR_FORMAT
+    assert srv.stop() == 0
+
+
+def test_errors_stay_with_their_request(codec):
+    """A corrupt stream and a non-finite field in one batch: only those two
+    requests fail; their neighbours complete normally."""
+    from paper_1903_07761_amd import _cz, fields
+
+    good = fields.gaussian_bumps(64, 9, dtype=torch.float64).cuda()
+    nanf = good.clone()
+    nanf.view(-1)[77] = float("nan")
+    p = codec.params(good, 16, "W3_ai", 1e-4)
+    ref, n = codec.compress(good, 16, "W3_ai", 1e-4)
+    ref = ref[:n].clone()
+    corrupt = ref.clone()
+    corrupt[64 + 8: 64 + 16] = torch.tensor([0xFF] * 8, dtype=torch.uint8, device="cuda")
+    bound = _cz.compress_bound(p)
+    o = [torch.empty(bound, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    r = [torch.empty_like(good) for _ in range(2)]
+    torch.cuda.synchronize()
+    srv = _cz.Server(codec.ctx, 200e9, 64)
+    ts = [srv.submit(0, p, good.data_ptr(), 0, o[0].data_ptr(), bound),
+          srv.submit(0, p, nanf.data_ptr(), 0, o[1].data_ptr(), bound),
+          srv.submit(1, p, corrupt.data_ptr(), n, r[0].data_ptr(), good.numel() * 8),
+          srv.submit(1, p, ref.data_ptr(), n, r[1].data_ptr(), good.numel() * 8),
+          srv.submit(0, p, good.data_ptr(), 0, o[2].data_ptr(), bound)]
+    st = [srv.wait(t) for t in ts]
+    assert srv.stop() == 0
+    assert st == [0, _cz.ERR_NONFINITE, _cz.ERR_FORMAT, 0, 0]
+    assert torch.equal(o[0][:n], ref) and torch.equal(o[2][:n], ref)
+    one = codec.decompress(ref, n)
+    torch.cuda.synchronize()
+    assert torch.equal(r[1], one)
