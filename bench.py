@@ -305,12 +305,149 @@ def main_c4(args):
         raise SystemExit("batched output differs from the single-field calls")
 
 
+def c5_requests(n_req: int = 2000):
+    """Request mix of the serving workload: edge = clamp(exp(N(ln 181, 0.5)),
+    64, 512) rounded to a multiple of 32, float32 with probability 0.7, scheme
+    uniform, eps in {1e-2, 1e-3, 1e-4} of range, bubble cloud or Gaussian bumps
+    at even odds, compress or decompress at even odds, N = 32; seed 1907."""
+    import numpy as np
+
+    rng = np.random.Generator(np.random.PCG64(1907))
+    out = []
+    for _ in range(n_req):
+        edge = int(round(min(512.0, max(64.0, math.exp(rng.normal(math.log(181.0), 0.5)))) / 32.0)) * 32
+        elem = 4 if rng.random() < 0.7 else 8
+        scheme = ["W4", "W4_li", "W3_ai"][int(rng.integers(0, 3))]
+        frac = [1e-2, 1e-3, 1e-4][int(rng.integers(0, 3))]
+        gen = "bubbles" if rng.random() < 0.5 else "bumps"
+        op = 0 if rng.random() < 0.5 else 1
+        out.append((edge, elem, scheme, frac, gen, op))
+    return out
+
+
+def main_c5(args):
+    """Serving: Poisson arrivals of the request mix at rates from 1/4 to 4x the
+    plain path's capacity, served by the continuous-batching scheduler and by
+    the plain FIFO (one request per launch, max_inflight 1); p50 / p99 latency
+    (completion - scheduled arrival) and GB/s of raw field."""
+    import numpy as np
+    import torch
+
+    from paper_1903_07761_amd import _cz
+    from paper_1903_07761_amd import fields as G
+    from paper_1903_07761_amd.codec import Codec
+
+    dev = torch.device("cuda", 0)
+    codec = Codec(0)
+    reqs = c5_requests(args.requests)
+    dt = {4: torch.float32, 8: torch.float64}
+    pool = {}
+    for edge, elem, _, _, gen, _ in reqs:
+        k = (edge, elem, gen)
+        if k not in pool:
+            seed = 1907 * 1000 + len(pool)
+            f = (G.bubble_cloud(edge, seed, dtype=dt[elem], device=dev) if gen == "bubbles"
+                 else G.gaussian_bumps(edge, seed, dtype=dt[elem], device=dev))
+            pool[k] = (f, G.value_range(f))
+    log(f"c5: {len(reqs)} requests over {len(pool)} distinct fields")
+    # decompress inputs, compressed once (untimed); destination buffers shared
+    # by requests of one shape and direction (outputs are checked by the tests)
+    streams, dsts, specs = {}, {}, []
+    raw_total = 0
+    for edge, elem, scheme, frac, gen, op in reqs:
+        f, rng = pool[(edge, elem, gen)]
+        p = codec.params(f, 32, scheme, frac * rng)
+        raw = f.numel() * elem
+        raw_total += raw
+        if op == 1:
+            sk = (edge, elem, gen, scheme, frac)
+            if sk not in streams:
+                buf, n = codec.compress(f, 32, scheme, frac * rng)
+                streams[sk] = (buf[:n].clone(), n)
+                del buf
+            src, sbytes = streams[sk]
+            dk = (edge, elem, 1)
+            if dk not in dsts:
+                dsts[dk] = torch.empty(raw, dtype=torch.uint8, device=dev)
+            specs.append((1, p, src.data_ptr(), sbytes, dsts[dk].data_ptr(), raw))
+        else:
+            dk = (edge, elem, 0)
+            if dk not in dsts:
+                dsts[dk] = torch.empty(_cz.compress_bound(p), dtype=torch.uint8, device=dev)
+            specs.append((0, p, f.data_ptr(), 0, dsts[dk].data_ptr(), dsts[dk].numel()))
+    torch.cuda.synchronize()
+    budget = 200e9
+
+    def serve(max_inflight, rate):
+        """rate None: all requests arrive at t = 0 (saturation)."""
+        srv = _cz.Server(codec.ctx, budget, max_inflight)
+        n = len(specs)
+        gaps = np.random.Generator(np.random.PCG64(1908)).exponential(1.0, n)
+        arr = np.zeros(n) if rate is None else np.cumsum(gaps) / rate
+        t0 = srv.time() + 0.01
+        tickets, lag = [], 0.0
+        for i, (op, p, src, sb, dst, cap) in enumerate(specs):
+            due = t0 + arr[i]
+            while srv.time() < due:
+                pass
+            lag = max(lag, srv.time() - due)
+            tickets.append(srv.submit(op, p, src, sb, dst, cap, tag=i))
+        for t in tickets:
+            rc = srv.wait(t)
+            if rc != 0:
+                raise SystemExit(f"request {t} failed: {_cz.strerror(rc)}")
+        info = [srv.poll(t) for t in tickets]
+        if srv.stop() != 0:
+            raise SystemExit("server reported a device failure")
+        lat = np.array([d["t_done"] - (t0 + arr[i]) for i, d in enumerate(info)])
+        span = max(d["t_done"] for d in info) - t0
+        return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                "GBps": round(raw_total / span / 1e9, 1), "makespan_s": round(span, 4),
+                "max_submit_lag_ms": round(float(lag) * 1e3, 3)}
+
+    log("c5: warm-up and plain-path capacity")
+    serve(256, None)
+    sat_plain = serve(1, None)
+    sat_batch = serve(256, None)
+    cap = len(specs) / sat_plain["makespan_s"]
+    sweep = []
+    for mult in (0.25, 0.5, 1.0, 2.0, 4.0):
+        rate = mult * cap
+        b = serve(256, rate)
+        f = serve(1, rate)
+        sweep.append({"rate_x_plain_capacity": mult, "rate_per_s": round(rate, 1), "batched": b, "plain_fifo": f})
+        log(f"c5 x{mult}: batched {b} plain {f}")
+    line = {
+        "metric": "GB/s raw field (FWT+threshold+pack, and inverse)",
+        "value": sat_batch["GBps"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(sat_batch["makespan_s"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(specs)} serving requests (edges 64..512, block 32, 70% float32, "
+                               "compress/decompress 50/50, eps 1e-2..1e-4 of range), budget 200e9 B",
+                   "raw_bytes": raw_total, "distinct_fields": len(pool)},
+        "saturated": {"batched": sat_batch, "plain_fifo": sat_plain},
+        "plain_capacity_req_per_s": round(cap, 1),
+        "poisson_sweep": sweep,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4", "c5"])
+    ap.add_argument("--requests", type=int, default=2000, help="c5: number of serving requests")
     ap.add_argument("--cpu-blocks", type=int, default=400, help="oracle sample: blocks per field")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-zlib", action="store_true", help="skip the host lossless stage and the C2 sweep")
@@ -322,6 +459,8 @@ def main():
 
     if args.workload == "c4":
         return main_c4(args)
+    if args.workload == "c5":
+        return main_c5(args)
 
     import torch
 
