@@ -493,10 +493,8 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int j = 0; j < Z; ++j) {
-                bad |= !finite(c[r][g * Z + j]);
+            for (int j = 0; j < Z; ++j)
                 lds[j * G::PS + (yq + r * G::YR) * G::PX + x] = c[r][g * Z + j];
-            }
         if (g + 1 < N / Z)
             load_planes<T, N, Z, R>(a, b, g + 1, lane_off, c);
         lds_barrier();
@@ -554,7 +552,11 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
         }
     }
 
-    // decimation: keep the 4^3 corner and |c| >= eps (compared in double)
+    // decimation: keep the 4^3 corner and |c| >= eps (compared in double).
+    // Every input sample reaches some coefficient with a non-zero weight, so a
+    // non-finite input always leaves a non-finite coefficient: checking the
+    // coefficients covers the input too (and keeps the loaded values from
+    // staying live until here).
     uint32_t keepbits[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -935,9 +937,7 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
         bool bad = false;
         for (int qq = tid; qq < N * N * N; qq += NT) {
             const int x = qq % N, y = (qq / N) % N, z = qq / (N * N);
-            const T v = src[(size_t)z * plane + (size_t)y * a.nx + x];
-            bad |= !finite(v);
-            blkS[qq] = v;
+            blkS[qq] = src[(size_t)z * plane + (size_t)y * a.nx + x];
         }
         gbarrier<NT>();
         scratch_levels_fwd<T, S, N, N, NT>(blkS);
