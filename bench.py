@@ -151,6 +151,9 @@ def c2_sweep(codec, torch):
 
 
 def traffic_record(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when
+    there is none or the kernel sources changed since they were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -593,7 +596,13 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "frac_of_copy": round(achieved / copy_gbps, 4),
-                     "traffic": tr, "fwd_GBps_algo": round(fwd_rate, 1), "inv_GBps_algo": round(inv_rate, 1)},
+                     "traffic": round(tr["bytes_per_launch"]) if tr else None,
+                     "traffic_detail": ({"fetch_bytes": round(tr["fetch_bytes_per_launch"]),
+                                         "write_bytes": round(tr["write_bytes_per_launch"]),
+                                         "algorithmic_bytes": round(tr["algorithmic_bytes_per_launch"]),
+                                         "source": "profiles/hbm_traffic_c3_1024cubed_f64_w3ai.md"} if tr else None),
+                     "algorithmic_bytes_per_launch": round(sum(algo) / len(algo)),
+                     "fwd_GBps_algo": round(fwd_rate, 1), "inv_GBps_algo": round(inv_rate, 1)},
         "cpu_baseline": cpu,
         "c2_eps_sweep": sweep,
         "paper_reference": {"W3_ai_stage1_MBps": {"compress": 277, "decompress": 215},
