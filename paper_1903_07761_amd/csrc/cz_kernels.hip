@@ -804,72 +804,200 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
 }
 
 // ------------------------------------------------- scratch-staged blocks
-// Blocks too large for a CU (N = 64: 1 MiB float, 2 MiB double) are
-// transformed in a per-workgroup scratch slot in global memory (L2/MALL
-// resident), one line per thread per pass, with full workgroup barriers
-// between passes (those must order global memory).  The arithmetic is the
-// same line code as the on-chip kernels; only the staging differs.
+// Blocks too large for a CU (N = 64: 1 MiB float, 2 MiB double) live in a
+// per-workgroup scratch slot in global memory between passes.  Each level's
+// x- and y-lines run on chunks of z-planes staged through LDS (row pitch
+// n + 1), the finest level reading its rows straight from the field (forward)
+// or writing them straight to it (inverse); the z-lines run in registers,
+// one column per thread at a time, lanes along x; the coarse levels from
+// (N/2)^3 (float) or (N/4)^3 (double) down run entirely in LDS.  Full
+// workgroup barriers separate passes that communicate through the scratch
+// slot (they must order global memory).
 
 template <int NT>
 __device__ __forceinline__ void gbarrier() { __syncthreads(); }
 
-// One axis pass (fwd or inv) over every line of [0,n)^3 of the N^3 block at
-// S (q = x + N (y + N z)); lanes run along x for y- and z-lines.
-template <typename T, int S, int N, int n, int AXIS, bool INV, int NT>
-__device__ __forceinline__ void scratch_pass(T *blk)
+template <typename T, int N>
+struct Big {
+    static constexpr int NT = SCRATCH_THREADS;
+    static constexpr int TAIL = sizeof(T) == 4 ? N / 2 : N / 4;  // edge of the LDS-resident levels
+    static constexpr int WORDS = N * N * N / 64;
+    static constexpr size_t CHUNK_BYTES = (sizeof(T) == 4 ? 8 : 4) * (size_t)N * (N + 1) * sizeof(T);
+    static constexpr size_t TAIL_BYTES = (size_t)TAIL * TAIL * (TAIL + 1) * sizeof(T);
+    static constexpr size_t WORD_BYTES = (size_t)WORDS * (sizeof(uint64_t) + sizeof(uint32_t));
+    static constexpr size_t M1 = CHUNK_BYTES > TAIL_BYTES ? CHUNK_BYTES : TAIL_BYTES;
+    static constexpr size_t LDS_BYTES = M1 > WORD_BYTES ? M1 : WORD_BYTES;
+    // planes per LDS chunk at level n: the largest power of two that fits
+    static constexpr int chunk(int n)
+    {
+        int z = n;
+        while (z > 1 && (size_t)z * n * (n + 1) * sizeof(T) > CHUNK_BYTES)
+            z /= 2;
+        return z;
+    }
+};
+
+// x- and y-lines of one level (forward: x then y; inverse: y then x) on the
+// planes [0, n) of [0, n)^2, ZC planes at a time through LDS.  Rows are read
+// from src and written to dst (strides in elements; src may equal dst).
+template <typename T, int S, int n, int ZC, bool INV, int NT>
+__device__ __forceinline__ void xy_level(const T *src, size_t sps, size_t srs, T *dst, size_t dps, size_t drs, T *lds)
 {
-    constexpr int PY = N, PZ = N * N;
-    for (int l = threadIdx.x; l < n * n; l += NT) {
-        const int i = l % n, j = l / n;
-        int base, stride;
-        if constexpr (AXIS == 0) {
-            base = i * PY + j * PZ;
-            stride = 1;
-        } else if constexpr (AXIS == 1) {
-            base = i + j * PZ;
-            stride = PY;
-        } else {
-            base = i + j * PY;
-            stride = PZ;
+    constexpr int PX = n + 1, PS = n * PX;
+    for (int z0 = 0; z0 < n; z0 += ZC) {
+#pragma unroll 8
+        for (int e = threadIdx.x; e < ZC * n * n; e += NT) {
+            const int x = e % n, y = (e / n) % n, j = e / (n * n);
+            lds[j * PS + y * PX + x] = src[(size_t)(z0 + j) * sps + (size_t)y * srs + x];
         }
+        lds_barrier();
+        if constexpr (!INV) {
+            stage_lines<T, S, n, ZC, NT, PX, PS, 0, false>(lds);
+            lds_barrier();
+            stage_lines<T, S, n, ZC, NT, PX, PS, 1, false>(lds);
+        } else {
+            stage_lines<T, S, n, ZC, NT, PX, PS, 1, true>(lds);
+            lds_barrier();
+            stage_lines<T, S, n, ZC, NT, PX, PS, 0, true>(lds);
+        }
+        lds_barrier();
+#pragma unroll 8
+        for (int e = threadIdx.x; e < ZC * n * n; e += NT) {
+            const int x = e % n, y = (e / n) % n, j = e / (n * n);
+            dst[(size_t)(z0 + j) * dps + (size_t)y * drs + x] = lds[j * PS + y * PX + x];
+        }
+        lds_barrier();
+    }
+}
+
+// z-lines of one level on the columns of [0, n)^2 of the scratch block.
+template <typename T, int S, int N, int n, bool INV, int NT>
+__device__ __forceinline__ void z_level(T *blk)
+{
+#pragma unroll 1
+    for (int l = threadIdx.x; l < n * n; l += NT) {
+        const int x = l % n, y = l / n;
         T v[n];
 #pragma unroll
         for (int k = 0; k < n; ++k)
-            v[k] = blk[base + k * stride];
+            v[k] = blk[(size_t)k * N * N + y * N + x];
         if constexpr (INV)
             line_inv<T, S, n>(v);
         else
             line_fwd<T, S, n>(v);
 #pragma unroll
         for (int k = 0; k < n; ++k)
-            blk[base + k * stride] = v[k];
+            blk[(size_t)k * N * N + y * N + x] = v[k];
     }
 }
 
-template <typename T, int S, int N, int n, int NT>
-__device__ __forceinline__ void scratch_levels_fwd(T *blk)
+// All lines of one axis of [0, n)^3 in LDS (row pitch PY, slab pitch PZ),
+// NT threads, each taking lines until none is left.
+template <typename T, int S, int n, int AXIS, bool INV, int PY, int PZ, int NT>
+__device__ __forceinline__ void lds_lines_all(T *lds)
 {
-    scratch_pass<T, S, N, n, 0, false, NT>(blk);
-    gbarrier<NT>();
-    scratch_pass<T, S, N, n, 1, false, NT>(blk);
-    gbarrier<NT>();
-    scratch_pass<T, S, N, n, 2, false, NT>(blk);
-    gbarrier<NT>();
-    if constexpr (n / 2 >= 8)
-        scratch_levels_fwd<T, S, N, n / 2, NT>(blk);
+#pragma unroll 1
+    for (int t = threadIdx.x; t < n * n; t += NT) {
+        const int i = t % n, j = t / n;
+        const int base = AXIS == 0 ? i * PY + j * PZ : AXIS == 1 ? i + j * PZ : i + j * PY;
+        constexpr int stride = AXIS == 0 ? 1 : AXIS == 1 ? PY : PZ;
+        T v[n];
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            v[k] = lds[base + k * stride];
+        if constexpr (INV)
+            line_inv<T, S, n>(v);
+        else
+            line_fwd<T, S, n>(v);
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            lds[base + k * stride] = v[k];
+    }
 }
 
-template <typename T, int S, int N, int n, int NT>
-__device__ __forceinline__ void scratch_levels_inv(T *blk)
+template <typename T, int S, int n, int PY, int PZ, int NT>
+__device__ __forceinline__ void tail_fwd(T *lds)
+{
+    lds_lines_all<T, S, n, 0, false, PY, PZ, NT>(lds);
+    lds_barrier();
+    lds_lines_all<T, S, n, 1, false, PY, PZ, NT>(lds);
+    lds_barrier();
+    lds_lines_all<T, S, n, 2, false, PY, PZ, NT>(lds);
+    lds_barrier();
+    if constexpr (n / 2 >= 8)
+        tail_fwd<T, S, n / 2, PY, PZ, NT>(lds);
+}
+
+template <typename T, int S, int n, int PY, int PZ, int NT>
+__device__ __forceinline__ void tail_inv(T *lds)
 {
     if constexpr (n / 2 >= 8)
-        scratch_levels_inv<T, S, N, n / 2, NT>(blk);
-    scratch_pass<T, S, N, n, 2, true, NT>(blk);
+        tail_inv<T, S, n / 2, PY, PZ, NT>(lds);
+    lds_lines_all<T, S, n, 2, true, PY, PZ, NT>(lds);
+    lds_barrier();
+    lds_lines_all<T, S, n, 1, true, PY, PZ, NT>(lds);
+    lds_barrier();
+    lds_lines_all<T, S, n, 0, true, PY, PZ, NT>(lds);
+    lds_barrier();
+}
+
+// Levels m, m/2, ..., 8 of the region [0, m)^3 of the scratch block, in LDS.
+template <typename T, int S, int N, int m, bool INV, int NT>
+__device__ __forceinline__ void tail_levels(T *blk, T *lds)
+{
+    constexpr int QX = m + 1, QS = m * QX;
+#pragma unroll 8
+    for (int e = threadIdx.x; e < m * m * m; e += NT) {
+        const int x = e % m, y = (e / m) % m, z = e / (m * m);
+        lds[z * QS + y * QX + x] = blk[(size_t)z * N * N + y * N + x];
+    }
+    lds_barrier();
+    if constexpr (INV)
+        tail_inv<T, S, m, QX, QS, NT>(lds);
+    else
+        tail_fwd<T, S, m, QX, QS, NT>(lds);
+#pragma unroll 8
+    for (int e = threadIdx.x; e < m * m * m; e += NT) {
+        const int x = e % m, y = (e / m) % m, z = e / (m * m);
+        blk[(size_t)z * N * N + y * N + x] = lds[z * QS + y * QX + x];
+    }
+}
+
+// Forward transform of a 64^3 block: field rows -> scratch slot.
+template <typename T, int S, int N, int NT>
+__device__ __forceinline__ void big_fwd(const T *src, size_t plane, size_t row, T *blk, T *lds)
+{
+    using B = Big<T, N>;
+    xy_level<T, S, N, B::chunk(N), false, NT>(src, plane, row, blk, (size_t)N * N, N, lds);
     gbarrier<NT>();
-    scratch_pass<T, S, N, n, 1, true, NT>(blk);
+    z_level<T, S, N, N, false, NT>(blk);
     gbarrier<NT>();
-    scratch_pass<T, S, N, n, 0, true, NT>(blk);
+    if constexpr (B::TAIL < N / 2) {
+        xy_level<T, S, N / 2, B::chunk(N / 2), false, NT>(blk, (size_t)N * N, N, blk, (size_t)N * N, N, lds);
+        gbarrier<NT>();
+        z_level<T, S, N, N / 2, false, NT>(blk);
+        gbarrier<NT>();
+    }
+    tail_levels<T, S, N, B::TAIL, false, NT>(blk, lds);
     gbarrier<NT>();
+}
+
+// Inverse transform of a 64^3 block: scratch slot -> field rows.
+template <typename T, int S, int N, int NT>
+__device__ __forceinline__ void big_inv(T *blk, T *dst, size_t plane, size_t row, T *lds)
+{
+    using B = Big<T, N>;
+    tail_levels<T, S, N, B::TAIL, true, NT>(blk, lds);
+    gbarrier<NT>();
+    if constexpr (B::TAIL < N / 2) {
+        z_level<T, S, N, N / 2, true, NT>(blk);
+        gbarrier<NT>();
+        xy_level<T, S, N / 2, B::chunk(N / 2), true, NT>(blk, (size_t)N * N, N, blk, (size_t)N * N, N, lds);
+        gbarrier<NT>();
+    }
+    z_level<T, S, N, N, true, NT>(blk);
+    gbarrier<NT>();
+    xy_level<T, S, N, B::chunk(N), true, NT>(blk, (size_t)N * N, N, dst, plane, row, lds);
 }
 
 // Workgroup-wide exclusive scan of W word counts (W a multiple of NT): thread
@@ -903,8 +1031,11 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
     constexpr int WORDS = N * N * N / 64;
     constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
     constexpr int WAVES = NT / 64;
-    __shared__ uint64_t s_words[WORDS];
-    __shared__ uint32_t s_pre[WORDS];
+    // LDS: line staging during the transform, then mask words and prefixes
+    __shared__ __align__(16) uint8_t lds_raw[Big<T, N>::LDS_BYTES];
+    T *lds = reinterpret_cast<T *>(lds_raw);
+    uint64_t *s_words = reinterpret_cast<uint64_t *>(lds_raw);
+    uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds_raw + WORDS * sizeof(uint64_t));
     __shared__ uint32_t s_scan[WAVES + 1];
     __shared__ uint64_t s_block;
     __shared__ uint32_t s_field;
@@ -935,12 +1066,7 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
         const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
         const T *src = static_cast<const T *>(a.src) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
         bool bad = false;
-        for (int qq = tid; qq < N * N * N; qq += NT) {
-            const int x = qq % N, y = (qq / N) % N, z = qq / (N * N);
-            blkS[qq] = src[(size_t)z * plane + (size_t)y * a.nx + x];
-        }
-        gbarrier<NT>();
-        scratch_levels_fwd<T, S, N, N, NT>(blkS);
+        big_fwd<T, S, N, NT>(src, plane, a.nx, blkS, lds);
 
         // decimation: wavefront w takes words w, w + WAVES, ...
         for (int w = wave; w < WORDS; w += WAVES) {
@@ -1002,8 +1128,11 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
     constexpr int WORDS = N * N * N / 64;
     constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
     constexpr int WAVES = NT / 64;
-    __shared__ uint64_t s_words[WORDS];
-    __shared__ uint32_t s_pre[WORDS];
+    // LDS: mask words and prefixes while unpacking, then line staging
+    __shared__ __align__(16) uint8_t lds_raw[Big<T, N>::LDS_BYTES];
+    T *lds = reinterpret_cast<T *>(lds_raw);
+    uint64_t *s_words = reinterpret_cast<uint64_t *>(lds_raw);
+    uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds_raw + WORDS * sizeof(uint64_t));
     __shared__ uint32_t s_scan[WAVES + 1];
     __shared__ uint64_t s_block;
     __shared__ uint32_t s_field;
@@ -1074,15 +1203,11 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
             blkS[w * 64 + (int)lane] = v;
         }
         gbarrier<NT>();
-        scratch_levels_inv<T, S, N, N, NT>(blkS);
         const uint32_t bx = (uint32_t)(b % a.nbx);
         const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
         const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
         T *dst = static_cast<T *>(a.dst) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
-        for (int qq = tid; qq < N * N * N; qq += NT) {
-            const int x = qq % N, y = (qq / N) % N, z = qq / (N * N);
-            dst[(size_t)z * plane + (size_t)y * a.nx + x] = blkS[qq];
-        }
+        big_inv<T, S, N, NT>(blkS, dst, plane, a.nx, lds);
         gbarrier<NT>();
     }
 }
