@@ -9,7 +9,7 @@ of the paper's kind and keeps the fastest per (N, precision, scheme) in a
 JSON table keyed by the device architecture; ``apply`` loads the table into
 a libcz context.
 
-    python -m paper_1903_07761_amd.autotune [--out FILE] [--edge 256] [--reps 5]
+    python -m paper_1903_07761_amd.autotune [--out FILE] [--edge 512] [--reps 5]
 """
 from __future__ import annotations
 
@@ -65,7 +65,7 @@ def _time_variant(codec, f, block, scheme, eps, reps):
     return statistics.median(fwd), statistics.median(inv), buf[:n].cpu().numpy().tobytes()
 
 
-def tune(codec, edge: int = 256, reps: int = 5, blocks=BLOCKS, elems=(4, 8), schemes=SCHEMES, log=print):
+def tune(codec, edge: int = 512, reps: int = 5, blocks=BLOCKS, elems=(4, 8), schemes=SCHEMES, log=print):
     """Time every variant of every (N, precision, scheme); return the table
     entry for this device: {key: {"variant", "fwd_ms", "inv_ms"}}."""
     out = {}
@@ -74,7 +74,7 @@ def tune(codec, edge: int = 256, reps: int = 5, blocks=BLOCKS, elems=(4, 8), sch
             nv = _cz.variant_count(N, elem)
             if nv == 0:
                 continue
-            n = max(edge, 8 * N)  # at least 512 blocks, more than the chip holds at once
+            n = max(edge, 8 * N)  # at least 512 blocks: more than the chip holds at once
             f = G.bubble_cloud(n, 1906, dtype=DTYPES[elem], device=codec.device)
             eps = 1e-3 * G.value_range(f)
             for s in schemes:
@@ -122,7 +122,7 @@ def apply(codec, table: dict | None = None, path: str = DEFAULT_TABLE) -> int:
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_TABLE)
-    ap.add_argument("--edge", type=int, default=256)
+    ap.add_argument("--edge", type=int, default=512)
     ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args(argv)
     from .codec import Codec

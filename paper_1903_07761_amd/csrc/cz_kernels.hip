@@ -1267,17 +1267,19 @@ __global__ void fold_status_kernel(const uint32_t *counters, int nclass, uint32_
 // Shape per (precision, N, variant): slab depth Z, columns per thread R and
 // (forward) planes kept in VGPRs ZP.
 //   variant 0: float blocks and double blocks up to 16^3 staged whole in LDS,
-//     one column per thread; a double 32^3 block (256 KiB) staged 16 slabs at a
-//     time (132 KiB of LDS) with two columns per thread (512 threads, 256
-//     VGPRs a lane).  After the finest level the double 32^3 path parks 14
-//     planes (118 KiB + the 35 KiB coarse region), float 32^3 parks 16.
-//   variant 1: half the slab depth (N = 16, 32); float 32^3 with two columns
-//     per thread.
+//     one column per thread.  A double 32^3 block (256 KiB) is staged 16 slabs
+//     at a time (132 KiB of LDS), one column per thread (1024 threads, 128
+//     VGPRs a lane); after the finest level 14 planes of details are parked in
+//     LDS (118 KiB + the 35 KiB coarse region).  Float 32^3 parks 16 planes.
+//   variant 1: half the slab depth (N = 16, 32); two columns per thread at
+//     N = 32.
+//   variant 2 (double 32^3 only): 16 slabs at a time, two columns per thread
+//     (512 threads, 256 VGPRs a lane).
 template <typename T, int N, int V>
 struct Shape {
     static constexpr bool big = sizeof(T) == 8 && N >= 32;
     static constexpr int Z = (V == 1 && N >= 16) ? (big ? N / 4 : N / 2) : (big ? N / 2 : N);
-    static constexpr int R = (big || (V == 1 && N == 32)) ? 2 : 1;
+    static constexpr int R = (V == 2 && big) || (V == 1 && N == 32) ? 2 : 1;
     static constexpr int ZP = N < 32 ? N : (big ? N / 2 + 2 : N / 2);
     static constexpr int NT = N * N / R;
 };
@@ -1339,9 +1341,13 @@ static hipError_t scratch_dispatch(bool inverse, const Queue &q, int grid, hipSt
 #define CZ_VARIANTS(T, N, OP, ARGS)                                                                           \
     if (key.variant == 1) {                                                                                  \
         CZ_SCHEMES(T, N, 1, OP, ARGS)                                                                        \
-    } else {                                                                                                 \
-        CZ_SCHEMES(T, N, 0, OP, ARGS)                                                                        \
-    }
+    }                                                                                                        \
+    if constexpr (sizeof(T) == 8 && N == 32) {                                                               \
+        if (key.variant == 2) {                                                                              \
+            CZ_SCHEMES(T, N, 2, OP, ARGS)                                                                    \
+        }                                                                                                    \
+    }                                                                                                        \
+    CZ_SCHEMES(T, N, 0, OP, ARGS)
 #define CZ_DISPATCH(T, OP, ARGS)                                                                              \
     switch (key.block) {                                                                                     \
     case 8: CZ_SCHEMES(T, 8, 0, OP, ARGS)                                                                    \
@@ -1413,8 +1419,9 @@ bool fwd_one_block_per_workgroup(const KernelKey &key) { return key.block <= 32;
 // working set in the last-level cache at the price of idle CUs.
 int variant_count(uint32_t block, uint32_t elem_bytes)
 {
-    (void)elem_bytes;
-    return (block == 16 || block == 32) ? 2 : block == 64 ? 3 : 1;
+    if (block == 32)
+        return elem_bytes == 8 ? 3 : 2;
+    return block == 16 ? 2 : block == 64 ? 3 : 1;
 }
 
 int grid_cap(const KernelKey &key)
