@@ -132,8 +132,9 @@ def zlib_ratio(stream_dev, nbytes: int, raw: int) -> float:
 
 
 def c2_sweep(codec, torch):
-    """512^3 float32 bubble cloud, W4_li, 32^3 blocks: CR before / after zlib,
-    PSNR and max error for eps in {1e-2, 1e-3, 1e-4} of the range."""
+    """512^3 float32 bubble cloud, W4_li, 32^3 blocks: CR before / after zlib
+    (plain, byte-shuffled, and with Z4 / Z8 zeroing before the shuffle), PSNR
+    and max error for eps in {1e-2, 1e-3, 1e-4} of the range."""
     from paper_1903_07761_amd import fields as G
     from paper_1903_07761_amd import metrics
 
@@ -142,11 +143,21 @@ def c2_sweep(codec, torch):
     raw = f.numel() * 4
     out = []
     for frac in (1e-2, 1e-3, 1e-4):
-        buf, n = codec.compress(f, 32, "W4_li", frac * rng)
+        eps = frac * rng
+        buf, n = codec.compress(f, 32, "W4_li", eps)
         rec = codec.decompress(buf, n)
         p, m = metrics.error_stats(f, rec)
-        out.append({"eps_frac": frac, "cr_stage1": round(raw / n, 3), "cr_zlib": round(zlib_ratio(buf, n, raw), 3),
-                    "psnr_db": round(p, 2), "max_err": float(f"{m:.4g}")})
+        row = {"eps_frac": frac, "cr_stage1": round(raw / n, 3), "cr_zlib": round(zlib_ratio(buf, n, raw), 3),
+               "cr_shuffle_zlib": round(zlib_ratio(codec.shuffle(buf, n, 4), n, raw), 3),
+               "psnr_db": round(p, 2), "max_err": float(f"{m:.4g}")}
+        # Z4 / Z8: zero the low mantissa bits of the detail coefficients, then shuffle
+        for bits in (4, 8):
+            z = buf[:n].clone()
+            codec.zero_details(z, n, codec.params(f, 32, "W4_li", eps), bits)
+            pz, _ = metrics.error_stats(f, codec.decompress(z, n))
+            row[f"z{bits}"] = {"cr_shuffle_zlib": round(zlib_ratio(codec.shuffle(z, n, 4), n, raw), 3),
+                               "psnr_db": round(pz, 2)}
+        out.append(row)
     return out
 
 

@@ -196,6 +196,30 @@ int cz_plan_run(cz_plan *plan, const void *const *srcs, const size_t *src_bytes,
 int cz_plan_result(cz_plan *plan, void *stream, size_t *h_out_bytes);
 void cz_plan_destroy(cz_plan *plan);
 
+/* ---------------------------------------------- lossless-stage preconditioning
+ *
+ * Sec. 2.3 ("Lossless compression", "Wavelet types") and Sec. 4.1 (Exp. 2):
+ * before the lossless coder the aggregate stream may be byte-shuffled, and the
+ * low bits of the detail coefficients zeroed (Z4 / Z8).
+ *
+ * cz_shuffle: byte j of element i of d_in (elem = 4 or 8 bytes, n = nbytes /
+ * elem whole elements) goes to d_out[j * n + i]; the nbytes % elem tail bytes
+ * are copied to the end unchanged.  cz_unshuffle is its inverse.  d_in (for
+ * cz_shuffle) or d_out (for cz_unshuffle) must be elem-aligned; the buffers
+ * must not overlap.  Asynchronous on `stream`; CZ_ERR_ARG on bad arguments.
+ *
+ * cz_zero_details: in place, clear the `bits` least significant bits of every
+ * stored detail coefficient of the stream d_stream (nbytes long, made with
+ * parameters p): every value outside the 4^3 coarse corner.  Keep decisions
+ * are unchanged (the stream was decimated with the exact coefficients); only
+ * values change, by less than 2^bits units in the last place.  bits <= 23
+ * (float) or 52 (double), else CZ_ERR_ARG.  Asynchronous; a record
+ * inconsistent with the offsets is left alone and CZ_ERR_FORMAT is latched
+ * for cz_get_status. */
+int cz_shuffle(const void *d_in, size_t nbytes, uint32_t elem, void *d_out, void *stream);
+int cz_unshuffle(const void *d_in, size_t nbytes, uint32_t elem, void *d_out, void *stream);
+int cz_zero_details(cz_ctx *ctx, const cz_params *p, void *d_stream, size_t nbytes, uint32_t bits, void *stream);
+
 /* ------------------------------------------------------------------ serving
  *
  * A scheduler for a stream of independent requests (the in-situ use of

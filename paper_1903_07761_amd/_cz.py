@@ -84,6 +84,12 @@ def lib() -> ctypes.CDLL:
         L.cz_plan_result.restype = i32
         L.cz_plan_destroy.argtypes = [vp]
         L.cz_plan_destroy.restype = None
+        L.cz_shuffle.argtypes = [vp, sz, u32, vp, vp]
+        L.cz_shuffle.restype = i32
+        L.cz_unshuffle.argtypes = [vp, sz, u32, vp, vp]
+        L.cz_unshuffle.restype = i32
+        L.cz_zero_details.argtypes = [vp, P, vp, sz, u32, vp]
+        L.cz_zero_details.restype = i32
         L.cz_server_start.argtypes = [vp, sz, i32, PP]
         L.cz_server_start.restype = i32
         L.cz_submit.argtypes = [vp, ctypes.POINTER(cz_request), ctypes.POINTER(u64)]
@@ -159,6 +165,9 @@ class Context:
 
     def get_status(self, stream: int = 0) -> int:
         return lib().cz_get_status(self.handle, stream)
+
+    def zero_details(self, p: cz_params, d_stream: int, nbytes: int, bits: int, stream: int = 0):
+        _check(lib().cz_zero_details(self.handle, ctypes.byref(p), d_stream, nbytes, bits, stream), "cz_zero_details")
 
     def set_variant(self, block: int, elem_bytes: int, scheme, variant: int):
         s = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
@@ -297,3 +306,11 @@ class Server:
             self.stop()
         except Exception:
             pass
+
+
+def shuffle(d_in: int, nbytes: int, elem: int, d_out: int, stream: int = 0):
+    _check(lib().cz_shuffle(d_in, nbytes, elem, d_out, stream), "cz_shuffle")
+
+
+def unshuffle(d_in: int, nbytes: int, elem: int, d_out: int, stream: int = 0):
+    _check(lib().cz_unshuffle(d_in, nbytes, elem, d_out, stream), "cz_unshuffle")

@@ -102,5 +102,23 @@ class Codec:
                                   [o.numel() * o.element_size() for o in outs], _stream_handle(self.device))
         return outs
 
+    def shuffle(self, buf: torch.Tensor, nbytes: int, elem: int = 4, out: torch.Tensor | None = None):
+        """Byte-shuffle the first nbytes of a device buffer (element size elem)."""
+        if out is None:
+            out = torch.empty(nbytes, dtype=torch.uint8, device=buf.device)
+        _cz.shuffle(buf.data_ptr(), nbytes, elem, out.data_ptr(), _stream_handle(buf.device))
+        return out
+
+    def unshuffle(self, buf: torch.Tensor, nbytes: int, elem: int = 4, out: torch.Tensor | None = None):
+        if out is None:
+            out = torch.empty(nbytes, dtype=torch.uint8, device=buf.device)
+        _cz.unshuffle(buf.data_ptr(), nbytes, elem, out.data_ptr(), _stream_handle(buf.device))
+        return out
+
+    def zero_details(self, buf: torch.Tensor, nbytes: int, p: _cz.cz_params, bits: int):
+        """Z-zeroing of the detail coefficients of a device stream, in place."""
+        self.ctx.zero_details(p, buf.data_ptr(), nbytes, bits, _stream_handle(buf.device))
+        return buf
+
     def plan(self, op: str, ps) -> _cz.Plan:
         return _cz.Plan(self.ctx, op, ps)
