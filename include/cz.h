@@ -220,6 +220,45 @@ int cz_shuffle(const void *d_in, size_t nbytes, uint32_t elem, void *d_out, void
 int cz_unshuffle(const void *d_in, size_t nbytes, uint32_t elem, void *d_out, void *stream);
 int cz_zero_details(cz_ctx *ctx, const cz_params *p, void *d_stream, size_t nbytes, uint32_t bits, void *stream);
 
+/* ------------------------------------------------------------ random access
+ *
+ * Sec. 2.3 ("Data decompression"): decompression works block by block; a
+ * reader fetches only the records it needs through the offsets table and
+ * keeps recently decoded blocks in a cache.  Decoding uses the same inverse
+ * kernels, so every decoded block is bit-identical to the same block of a
+ * full cz_decompress.
+ *
+ * cz_decompress_blocks: decode the blocks h_blocks[0, n) (host array of block
+ * indices b = bx + nbx (by + nby bz), each < nblocks) of the stream d_in
+ * (in_bytes long, made with parameters p) into d_out: block k lands dense,
+ * [z][y][x] with x fastest, at element offset k N^3.  out_cap >= n N^3
+ * elem_bytes (else CZ_ERR_CAPACITY).  Asynchronous; a record inconsistent
+ * with the offsets is left unwritten and CZ_ERR_FORMAT latched for
+ * cz_get_status.  Uses the context's workspace like cz_decompress.
+ *
+ * cz_cache: a device pool of capacity_blocks decoded N^3 blocks of one stream
+ * (parameters p), least recently used replacement.  cz_cache_fetch makes the
+ * blocks h_blocks[0, n) resident (n <= capacity; repeated blocks allowed),
+ * decoding only those not already in the pool, and returns in h_ptrs[i] the
+ * device address of block h_blocks[i] (dense [z][y][x]); the addresses stay
+ * valid until a later fetch evicts them.  Passing another stream buffer or
+ * size empties the pool first.  cz_cache_region decodes (through the pool)
+ * the box origin[0..2] (x, y, z) + [0, extent) of the field into d_out
+ * ([ez][ey][ex], x fastest); the blocks it touches must fit the pool.
+ * cz_cache_stats returns the requested blocks served from the pool (hits) and
+ * decoded (misses).  A cache uses its context's work queue: its calls must
+ * not overlap with the context's other calls. */
+int cz_decompress_blocks(cz_ctx *ctx, const cz_params *p, const void *d_in, size_t in_bytes, const uint32_t *h_blocks,
+                         size_t n, void *d_out, size_t out_cap, void *stream);
+typedef struct cz_cache cz_cache;
+int cz_cache_create(cz_ctx *ctx, const cz_params *p, size_t capacity_blocks, cz_cache **out);
+int cz_cache_fetch(cz_cache *c, const void *d_in, size_t in_bytes, const uint32_t *h_blocks, size_t n,
+                   void **h_ptrs, void *stream);
+int cz_cache_region(cz_cache *c, const void *d_in, size_t in_bytes, const uint32_t origin[3], const uint32_t extent[3],
+                    void *d_out, size_t out_cap, void *stream);
+int cz_cache_stats(cz_cache *c, uint64_t *hits, uint64_t *misses);
+void cz_cache_destroy(cz_cache *c);
+
 /* ------------------------------------------------------------------ serving
  *
  * A scheduler for a stream of independent requests (the in-situ use of

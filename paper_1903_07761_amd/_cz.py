@@ -90,6 +90,19 @@ def lib() -> ctypes.CDLL:
         L.cz_unshuffle.restype = i32
         L.cz_zero_details.argtypes = [vp, P, vp, sz, u32, vp]
         L.cz_zero_details.restype = i32
+        PU32 = ctypes.POINTER(u32)
+        L.cz_decompress_blocks.argtypes = [vp, P, vp, sz, PU32, sz, vp, sz, vp]
+        L.cz_decompress_blocks.restype = i32
+        L.cz_cache_create.argtypes = [vp, P, sz, PP]
+        L.cz_cache_create.restype = i32
+        L.cz_cache_fetch.argtypes = [vp, vp, sz, PU32, sz, PP, vp]
+        L.cz_cache_fetch.restype = i32
+        L.cz_cache_region.argtypes = [vp, vp, sz, PU32, PU32, vp, sz, vp]
+        L.cz_cache_region.restype = i32
+        L.cz_cache_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.cz_cache_stats.restype = i32
+        L.cz_cache_destroy.argtypes = [vp]
+        L.cz_cache_destroy.restype = None
         L.cz_server_start.argtypes = [vp, sz, i32, PP]
         L.cz_server_start.restype = i32
         L.cz_submit.argtypes = [vp, ctypes.POINTER(cz_request), ctypes.POINTER(u64)]
@@ -165,6 +178,12 @@ class Context:
 
     def get_status(self, stream: int = 0) -> int:
         return lib().cz_get_status(self.handle, stream)
+
+    def decompress_blocks(self, p: cz_params, d_in: int, in_bytes: int, blocks, d_out: int, out_cap: int,
+                          stream: int = 0):
+        ids = _u32s(blocks)
+        _check(lib().cz_decompress_blocks(self.handle, ctypes.byref(p), d_in, in_bytes, ids, len(blocks), d_out,
+                                          out_cap, stream), "cz_decompress_blocks")
 
     def zero_details(self, p: cz_params, d_stream: int, nbytes: int, bits: int, stream: int = 0):
         _check(lib().cz_zero_details(self.handle, ctypes.byref(p), d_stream, nbytes, bits, stream), "cz_zero_details")
@@ -314,3 +333,46 @@ def shuffle(d_in: int, nbytes: int, elem: int, d_out: int, stream: int = 0):
 
 def unshuffle(d_in: int, nbytes: int, elem: int, d_out: int, stream: int = 0):
     _check(lib().cz_unshuffle(d_in, nbytes, elem, d_out, stream), "cz_unshuffle")
+
+
+def _u32s(vals):
+    arr = (ctypes.c_uint32 * max(len(vals), 1))()
+    for i, v in enumerate(vals):
+        arr[i] = int(v)
+    return arr
+
+
+class Cache:
+    """A device pool of decoded blocks of one stream (least recently used)."""
+
+    def __init__(self, ctx: Context, p: cz_params, capacity_blocks: int):
+        h = ctypes.c_void_p()
+        _check(lib().cz_cache_create(ctx.handle, ctypes.byref(p), capacity_blocks, ctypes.byref(h)), "cz_cache_create")
+        self.handle = h
+        self.ctx = ctx
+
+    def fetch(self, d_in: int, in_bytes: int, blocks, stream: int = 0):
+        ptrs = (ctypes.c_void_p * max(len(blocks), 1))()
+        _check(lib().cz_cache_fetch(self.handle, d_in, in_bytes, _u32s(blocks), len(blocks), ptrs, stream),
+               "cz_cache_fetch")
+        return [ptrs[i] for i in range(len(blocks))]
+
+    def region(self, d_in: int, in_bytes: int, origin, extent, d_out: int, out_cap: int, stream: int = 0):
+        _check(lib().cz_cache_region(self.handle, d_in, in_bytes, _u32s(origin), _u32s(extent), d_out, out_cap,
+                                     stream), "cz_cache_region")
+
+    def stats(self):
+        h, m = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(lib().cz_cache_stats(self.handle, ctypes.byref(h), ctypes.byref(m)), "cz_cache_stats")
+        return h.value, m.value
+
+    def close(self):
+        if self.handle:
+            lib().cz_cache_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -120,5 +120,29 @@ class Codec:
         self.ctx.zero_details(p, buf.data_ptr(), nbytes, bits, _stream_handle(buf.device))
         return buf
 
+    def decompress_blocks(self, buf: torch.Tensor, nbytes: int, p: _cz.cz_params, blocks,
+                          out: torch.Tensor | None = None) -> torch.Tensor:
+        """Decode the listed blocks of a device stream into [n, N, N, N]."""
+        N = p.block
+        if out is None:
+            out = torch.empty((len(blocks), N, N, N), dtype=_DTYPE[p.elem_bytes], device=buf.device)
+        self.ctx.decompress_blocks(p, buf.data_ptr(), nbytes, list(blocks), out.data_ptr(),
+                                   out.numel() * out.element_size(), _stream_handle(buf.device))
+        return out
+
+    def cache(self, p: _cz.cz_params, capacity_blocks: int) -> _cz.Cache:
+        return _cz.Cache(self.ctx, p, capacity_blocks)
+
+    def region(self, cache: _cz.Cache, buf: torch.Tensor, nbytes: int, p: _cz.cz_params, origin, extent,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+        """Decode the box origin (x, y, z) + extent of the field through a cache;
+        returns [ez, ey, ex]."""
+        ex, ey, ez = extent
+        if out is None:
+            out = torch.empty((ez, ey, ex), dtype=_DTYPE[p.elem_bytes], device=buf.device)
+        cache.region(buf.data_ptr(), nbytes, list(origin), list(extent), out.data_ptr(),
+                     out.numel() * out.element_size(), _stream_handle(buf.device))
+        return out
+
     def plan(self, op: str, ps) -> _cz.Plan:
         return _cz.Plan(self.ctx, op, ps)

@@ -124,6 +124,7 @@ czk::FieldDesc describe(const cz_params &p, uint64_t nb, bool forward)
     d.nby = p.ny / p.block;
     d.nblocks = nb;
     d.p0 = payload_start(nb);
+    d.rblocks = nb;
     d.eps = p.epsilon;
     d.eps_f = eps_float(p.epsilon);
     if (forward)
@@ -364,7 +365,8 @@ int cz_create(cz_ctx **out, int device)
                     hipMalloc(&ctx->one, sizeof(czk::FieldDesc)) == hipSuccess &&
                     hipMemset(ctx->work, 0, sizeof(czk::CzWork)) == hipSuccess &&
                     hipHostMalloc(&ctx->pinned, sizeof(czk::CzWork), hipHostMallocDefault) == hipSuccess &&
-                    ctx->flags.ensure(4096 * sizeof(uint64_t)) == CZ_OK && ctx->batch.init() == CZ_OK;
+                    ctx->flags.ensure(4096 * sizeof(uint64_t)) == CZ_OK && ctx->batch.init() == CZ_OK &&
+                    ctx->sel.init() == CZ_OK;
     if (!ok) {
         cz_destroy(ctx);
         return CZ_ERR_HIP;
@@ -382,6 +384,7 @@ void cz_destroy(cz_ctx *ctx)
     ctx->flags.release();
     ctx->scratch.release();
     ctx->batch.release();
+    ctx->sel.release();
     if (ctx->work)
         (void)hipFree(ctx->work);
     if (ctx->one)

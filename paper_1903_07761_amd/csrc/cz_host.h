@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <tuple>
 #include <vector>
 
@@ -169,6 +170,58 @@ struct DeviceGuard {
     }
 };
 
+// A pinned host array uploaded in stream order to a device array; the host
+// side is rewritten only after the previous upload has left it.
+struct Staging {
+    DevBuf dev;
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+
+    int init()
+    {
+        if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(done, nullptr) != hipSuccess)
+            return CZ_ERR_HIP;
+        return CZ_OK;
+    }
+    int upload(const void *src, size_t bytes, hipStream_t st)
+    {
+        if (hipEventSynchronize(done) != hipSuccess)
+            return CZ_ERR_HIP;
+        if (bytes > cap) {
+            if (host)
+                (void)hipHostFree(host);
+            host = nullptr;
+            cap = 0;
+            if (hipHostMalloc(&host, bytes, hipHostMallocDefault) != hipSuccess)
+                return CZ_ERR_HIP;
+            cap = bytes;
+        }
+        int rc = dev.ensure(bytes);
+        if (rc != CZ_OK)
+            return rc;
+        std::memcpy(host, src, bytes);
+        if (hipMemcpyAsync(dev.ptr, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipEventRecord(done, st) != hipSuccess)
+            return CZ_ERR_HIP;
+        return CZ_OK;
+    }
+    void release()
+    {
+        if (done)
+            (void)hipEventSynchronize(done);
+        dev.release();
+        if (host)
+            (void)hipHostFree(host);
+        if (done)
+            (void)hipEventDestroy(done);
+        host = nullptr;
+        done = nullptr;
+        cap = 0;
+    }
+};
+
 int check_params(const cz_params *p, uint64_t *nblocks);
 uint64_t payload_start(uint64_t nblocks);
 uint64_t bound_of(const cz_params &p, uint64_t nb);
@@ -182,6 +235,11 @@ void stage_batch(BatchWork &w, const Layout &L, const cz_params *ps, const void 
 int enqueue_batch(BatchWork &w, const Layout &L, uint32_t *status, bool per_field, hipStream_t st);
 int check_batch_buffers(const Layout &L, const cz_params *ps, const void *const *srcs, const size_t *src_bytes,
                         void *const *dsts, const size_t *dst_caps, size_t *need);
+czk::KernelKey key_of(const cz_ctx *ctx, const cz_params &p);
+czk::FieldDesc describe(const cz_params &p, uint64_t nb, bool forward);
+int grid_for(const cz_ctx *ctx, const czk::KernelKey &key, bool inverse, uint64_t tickets);
+size_t scratch_need(const czk::KernelKey &key, int grid);
+czk::Queue work_queue(cz_ctx *ctx);
 
 }  // namespace czh
 
@@ -195,6 +253,7 @@ struct cz_ctx {
     czk::FieldDesc *one = nullptr;  // device: the descriptor of a plain call (published by its prep kernel)
     uint8_t variant[4][2][3] = {};  // tuned kernel variant per (N, precision, scheme)
     czh::BatchWork batch;                // batch calls
+    czh::Staging sel;                    // selected-block decoding: (record, output block) pairs
 };
 
 #endif  // CZ_HOST_H

@@ -35,6 +35,8 @@ struct FieldDesc {
     uint64_t p0;          // payload start
     uint64_t payload;     // inverse: payload bytes available
     uint64_t first;       // the field's first ticket in its queue
+    const uint32_t *sel;  // inverse, optional: ticket k decodes record sel[k] (else record k)
+    uint64_t rblocks;     // inverse: records in the stream (sel entries must be below)
     double eps;
     float eps_f;          // smallest float >= eps (the same test for float data)
     uint32_t reserved;

@@ -348,6 +348,8 @@ struct FieldView {
     uint64_t *total;
     uint32_t nx, ny, nbx, nby;
     uint64_t nblocks, p0, payload, first;
+    const uint32_t *sel;
+    uint64_t rblocks;
     double eps;
     float eps_f;
 };
@@ -415,7 +417,7 @@ __device__ __forceinline__ const FieldDesc &field_desc(const Queue &q, uint32_t 
 __device__ __forceinline__ FieldView view_of(const FieldDesc &d)
 {
     return FieldView{d.src, d.dst, d.flags, d.total, d.nx, d.ny, d.nbx, d.nby, d.nblocks, d.p0, d.payload, d.first,
-                     d.eps, d.eps_f};
+                     d.sel, d.rblocks, d.eps, d.eps_f};
 }
 
 // The table is read through the constant address space: it is written before
@@ -430,7 +432,7 @@ __device__ __forceinline__ FieldView field_view(const Queue &q, uint32_t f)
     f = __builtin_amdgcn_readfirstlane(f);
     ConstDesc *d = (ConstDesc *)q.fields + f;
     return FieldView{d->src, d->dst, d->flags, d->total, d->nx, d->ny, d->nbx, d->nby, d->nblocks, d->p0,
-                     d->payload, d->first, d->eps, d->eps_f};
+                     d->payload, d->first, d->sel, d->rblocks, d->eps, d->eps_f};
 }
 
 // Latch STATUS_* bits for the queue and, when per-field words exist, for
@@ -666,6 +668,7 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
     __shared__ uint64_t s_block;
     __shared__ uint32_t s_field;
     __shared__ uint32_t s_ok;
+    __shared__ uint64_t s_rec, s_out;
 
     const int tid = threadIdx.x;
     const int x = tid % N, yq = tid / N;
@@ -676,14 +679,19 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
         if (tid == 0) {
             const uint64_t t = atomicAdd(q.ticket, 1u);
             uint32_t ok = 0, f = 0;
+            uint64_t rb = 0, ob = 0;
             if (t < q.ntickets) {
                 f = field_of_ticket(q, t);
                 const FieldView a = field_view(q, f);
                 const uint8_t *in = static_cast<const uint8_t *>(a.src);
                 const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
-                const uint64_t b = t - a.first;
-                const uint64_t o0 = offs[b], o1 = offs[b + 1];
-                ok = o1 >= o0 && o1 <= a.payload && o1 - o0 >= 8ull + G::MASK_BYTES;
+                const uint64_t k = t - a.first;
+                const uint64_t b = a.sel ? a.sel[2 * k] : k;  // the record this ticket decodes
+                rb = b;
+                ob = a.sel ? a.sel[2 * k + 1] : k;          // and the output block it fills
+                ok = b < a.rblocks;
+                const uint64_t o0 = ok ? offs[b] : 0, o1 = ok ? offs[b + 1] : 0;
+                ok = ok && o1 >= o0 && o1 <= a.payload && o1 - o0 >= 8ull + G::MASK_BYTES;
                 if (ok) {
                     const uint32_t nnz = *reinterpret_cast<const uint32_t *>(in + a.p0 + o0);
                     const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
@@ -695,6 +703,8 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
             s_block = t;
             s_field = f;
             s_ok = ok;
+            s_rec = rb;
+            s_out = ob;
         }
         lds_barrier();
         const uint64_t t = uniform64(s_block);
@@ -705,13 +715,13 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
             continue;
         }
         const FieldView a = field_view(q, s_field);
-        const uint64_t b = t - a.first;
+        const uint64_t b = uniform64(s_out);  // output block (the field's block index unless selected)
         const size_t plane = (size_t)a.nx * a.ny;
         const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;
         const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
         const uint8_t *in = static_cast<const uint8_t *>(a.src);
         const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
-        const uint8_t *rec = in + a.p0 + offs[b];
+        const uint8_t *rec = in + a.p0 + offs[uniform64(s_rec)];
         const uint32_t nnz = *reinterpret_cast<const uint32_t *>(rec);
         const uint64_t *mask = reinterpret_cast<const uint64_t *>(rec + 8);
         const rsrc_t vr = make_rsrc(rec + 8 + G::MASK_BYTES, nnz * (uint32_t)sizeof(T));
@@ -1137,6 +1147,7 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
     __shared__ uint64_t s_block;
     __shared__ uint32_t s_field;
     __shared__ uint32_t s_ok;
+    __shared__ uint64_t s_rec, s_out;
 
     const int tid = threadIdx.x;
     const uint32_t lane = lane_id();
@@ -1147,14 +1158,19 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
         if (tid == 0) {
             const uint64_t t = atomicAdd(q.ticket, 1u);
             uint32_t ok = 0, f = 0;
+            uint64_t rb = 0, ob = 0;
             if (t < q.ntickets) {
                 f = field_of_ticket(q, t);
                 const FieldView a = field_view(q, f);
                 const uint8_t *in = static_cast<const uint8_t *>(a.src);
                 const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
-                const uint64_t b = t - a.first;
-                const uint64_t o0 = offs[b], o1 = offs[b + 1];
-                ok = o1 >= o0 && o1 <= a.payload && o1 - o0 >= 8ull + MASK_BYTES;
+                const uint64_t k = t - a.first;
+                const uint64_t b = a.sel ? a.sel[2 * k] : k;  // the record this ticket decodes
+                rb = b;
+                ob = a.sel ? a.sel[2 * k + 1] : k;          // and the output block it fills
+                ok = b < a.rblocks;
+                const uint64_t o0 = ok ? offs[b] : 0, o1 = ok ? offs[b + 1] : 0;
+                ok = ok && o1 >= o0 && o1 <= a.payload && o1 - o0 >= 8ull + MASK_BYTES;
                 if (ok) {
                     const uint32_t nnz = *reinterpret_cast<const uint32_t *>(in + a.p0 + o0);
                     const uint64_t used = 8ull + MASK_BYTES + (uint64_t)nnz * sizeof(T);
@@ -1166,6 +1182,8 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
             s_block = t;
             s_field = f;
             s_ok = ok;
+            s_rec = rb;
+            s_out = ob;
         }
         gbarrier<NT>();
         const uint64_t t = uniform64(s_block);
@@ -1176,11 +1194,11 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
             continue;
         }
         const FieldView a = field_view(q, s_field);
-        const uint64_t b = t - a.first;
+        const uint64_t b = uniform64(s_out);  // output block (the field's block index unless selected)
         const size_t plane = (size_t)a.nx * a.ny;
         const uint8_t *in = static_cast<const uint8_t *>(a.src);
         const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + 64);
-        const uint8_t *rec = in + a.p0 + offs[b];
+        const uint8_t *rec = in + a.p0 + offs[uniform64(s_rec)];
         const uint32_t nnz = *reinterpret_cast<const uint32_t *>(rec);
         const uint64_t *mask = reinterpret_cast<const uint64_t *>(rec + 8);
         const rsrc_t vr = make_rsrc(rec + 8 + MASK_BYTES, nnz * (uint32_t)sizeof(T));
