@@ -118,6 +118,18 @@ size_t cz_compress_bound(const cz_params *p);
 int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_out, size_t out_cap,
                 uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream);
 
+/* In-situ extraction (Sec. 2.1: the compressor takes the quantity of
+ * interest out of the solver's blocks, whose cells hold all quantities):
+ * compress quantity `comp` of an interleaved state d_state, a C-order
+ * [nz][ny][nx][ncomp] array of the field type (cell (x, y, z) holds its
+ * ncomp quantities contiguously).  The blocks are read with strided loads
+ * straight from the state; the stream is byte-identical to cz_compress of the
+ * extracted field.  Other arguments and returns as cz_compress; CZ_ERR_ARG for
+ * comp >= ncomp, CZ_ERR_SHAPE when a block row of the state spans 2^31 bytes
+ * or more. */
+int cz_compress_strided(cz_ctx *ctx, const cz_params *p, const void *d_state, uint32_t ncomp, uint32_t comp,
+                        void *d_out, size_t out_cap, uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream);
+
 /* Rebuild the field from the stream d_in (in_bytes long) into d_field
  * (field_cap bytes).  With expected == NULL the 64-byte header is read back
  * (synchronous), and the call waits for completion and returns (and clears)

@@ -58,6 +58,9 @@ def lib() -> ctypes.CDLL:
         L.cz_compress_bound.restype = sz
         L.cz_compress.argtypes = [vp, P, vp, vp, sz, vp, ctypes.POINTER(sz), vp]
         L.cz_compress.restype = i32
+        L.cz_compress_strided.argtypes = [vp, P, vp, ctypes.c_uint32, ctypes.c_uint32, vp, sz, vp,
+                                          ctypes.POINTER(sz), vp]
+        L.cz_compress_strided.restype = i32
         L.cz_decompress.argtypes = [vp, P, vp, sz, vp, sz, vp]
         L.cz_decompress.restype = i32
         L.cz_get_status.argtypes = [vp, vp]
@@ -168,6 +171,16 @@ class Context:
                                ctypes.byref(nbytes) if sync else None, stream)
         if rc != OK:
             raise CzError(rc, "cz_compress", f"(required {nbytes.value} bytes)" if rc == ERR_CAPACITY else "")
+        return nbytes.value if sync else None
+
+    def compress_strided(self, p: cz_params, d_state: int, ncomp: int, comp: int, d_out: int, out_cap: int,
+                         stream: int = 0, d_out_bytes: int | None = None, sync: bool = True) -> int | None:
+        """cz_compress_strided; returns the stream size when sync."""
+        nbytes = ctypes.c_size_t(0)
+        rc = lib().cz_compress_strided(self.handle, ctypes.byref(p), d_state, ncomp, comp, d_out, out_cap,
+                                       d_out_bytes, ctypes.byref(nbytes) if sync else None, stream)
+        if rc != OK:
+            raise CzError(rc, "cz_compress_strided")
         return nbytes.value if sync else None
 
     def decompress(self, d_in: int, in_bytes: int, d_field: int, field_cap: int, stream: int = 0,

@@ -55,6 +55,20 @@ class Codec:
                               out_bytes.data_ptr() if out_bytes is not None else None, sync)
         return out, n
 
+    def compress_component(self, state: torch.Tensor, comp: int, block: int, scheme, epsilon: float,
+                           out: torch.Tensor | None = None):
+        """Compress quantity `comp` of a contiguous interleaved state
+        [nz, ny, nx, ncomp] straight from the state.  Returns (buffer, size)."""
+        assert state.is_cuda and state.is_contiguous() and state.dim() == 4
+        nz, ny, nx, ncomp = state.shape
+        p = _cz.params(nx, ny, nz, block, scheme, _ELEM[state.dtype], epsilon)
+        cap = _cz.compress_bound(p)
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=state.device)
+        n = self.ctx.compress_strided(p, state.data_ptr(), ncomp, comp, out.data_ptr(), out.numel(),
+                                      _stream_handle(state.device))
+        return out, n
+
     def decompress(self, stream_buf: torch.Tensor, nbytes: int, out: torch.Tensor | None = None,
                    expected: _cz.cz_params | None = None) -> torch.Tensor:
         """Rebuild the field from a device stream (header read back unless

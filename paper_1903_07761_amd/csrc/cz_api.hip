@@ -125,6 +125,7 @@ czk::FieldDesc describe(const cz_params &p, uint64_t nb, bool forward)
     d.nblocks = nb;
     d.p0 = payload_start(nb);
     d.rblocks = nb;
+    d.cstride = 1;
     d.eps = p.epsilon;
     d.eps_f = eps_float(p.epsilon);
     if (forward)
@@ -427,8 +428,8 @@ int cz_set_variant(cz_ctx *ctx, uint32_t block, uint32_t elem_bytes, uint32_t sc
     return CZ_OK;
 }
 
-int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_out, size_t out_cap,
-                uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream)
+static int compress_impl(cz_ctx *ctx, const cz_params *p, const void *d_field, uint32_t cs, void *d_out,
+                         size_t out_cap, uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream)
 {
     if (!ctx)
         return CZ_ERR_ARG;
@@ -454,6 +455,7 @@ int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_ou
     q.fields = q.publish = ctx->one;
     q.one = describe(*p, nb, true);
     q.one.src = d_field;
+    q.one.cstride = cs;
     q.one.dst = d_out;
     q.one.flags = static_cast<uint64_t *>(ctx->flags.ptr);
     q.one.total = &ctx->work->total;
@@ -478,6 +480,24 @@ int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_ou
         return take_status(ctx, st);
     }
     return CZ_OK;
+}
+
+int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_out, size_t out_cap,
+                uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream)
+{
+    return compress_impl(ctx, p, d_field, 1, d_out, out_cap, d_out_bytes, h_out_bytes, stream);
+}
+
+int cz_compress_strided(cz_ctx *ctx, const cz_params *p, const void *d_state, uint32_t ncomp, uint32_t comp,
+                        void *d_out, size_t out_cap, uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream)
+{
+    if (!p || ncomp == 0 || comp >= ncomp)
+        return CZ_ERR_ARG;
+    // a block row span of the state is addressed with 32-bit offsets
+    if ((uint64_t)p->nx * p->block * p->elem_bytes * ncomp >= (1ull << 31))
+        return CZ_ERR_SHAPE;
+    const uint8_t *src = d_state ? static_cast<const uint8_t *>(d_state) + (size_t)comp * p->elem_bytes : nullptr;
+    return compress_impl(ctx, p, src, ncomp, d_out, out_cap, d_out_bytes, h_out_bytes, stream);
 }
 
 int cz_read_header(const void *h_hdr, size_t n, cz_params *out, uint64_t *nblocks, uint64_t *total_bytes)

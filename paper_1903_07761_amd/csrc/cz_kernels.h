@@ -39,7 +39,7 @@ struct FieldDesc {
     uint64_t rblocks;     // inverse: records in the stream (sel entries must be below)
     double eps;
     float eps_f;          // smallest float >= eps (the same test for float data)
-    uint32_t reserved;
+    uint32_t cstride;     // forward: elements between consecutive cells of src (1 = a plain field)
     uint32_t header[16];  // forward: the 64-byte header, payload size 0
 };
 

@@ -352,6 +352,7 @@ struct FieldView {
     uint64_t rblocks;
     double eps;
     float eps_f;
+    uint32_t cs;  // element stride of the source (interleaved state), 1 for a plain field
 };
 
 template <typename T>
@@ -373,18 +374,20 @@ template <typename T, int N, int Z, int R>
 __device__ __forceinline__ void load_planes(const FieldView &a, uint64_t b, int g, uint32_t lane_off, T (*dst)[N])
 {
     using G = Geom<T, N, Z, R>;
-    const size_t plane = (size_t)a.nx * a.ny;
+    // source strides in elements (a.cs > 1: one quantity of an interleaved state)
+    const uint32_t row = a.nx * a.cs;
+    const size_t plane = (size_t)row * a.ny;
     const uint32_t bx = (uint32_t)(b % a.nbx);
     const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
     const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
-    const T *blk = static_cast<const T *>(a.src) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
-    const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
+    const T *blk = static_cast<const T *>(a.src) + ((size_t)bz * N * plane + (size_t)by * N * row + (size_t)bx * N * a.cs);
+    const uint32_t slab_bytes = ((uint32_t)(N - 1) * row + N * a.cs) * (uint32_t)sizeof(T);
 #pragma unroll
     for (int j = 0; j < Z; ++j) {
         const rsrc_t zr = make_rsrc(blk + (size_t)(g * Z + j) * plane, slab_bytes);
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            dst[r][g * Z + j] = buf_load<T>(zr, (lane_off + (uint32_t)(r * G::YR) * a.nx) * (uint32_t)sizeof(T));
+            dst[r][g * Z + j] = buf_load<T>(zr, (lane_off + (uint32_t)(r * G::YR) * row) * (uint32_t)sizeof(T));
     }
 }
 
@@ -417,7 +420,7 @@ __device__ __forceinline__ const FieldDesc &field_desc(const Queue &q, uint32_t 
 __device__ __forceinline__ FieldView view_of(const FieldDesc &d)
 {
     return FieldView{d.src, d.dst, d.flags, d.total, d.nx, d.ny, d.nbx, d.nby, d.nblocks, d.p0, d.payload, d.first,
-                     d.sel, d.rblocks, d.eps, d.eps_f};
+                     d.sel, d.rblocks, d.eps, d.eps_f, d.cstride};
 }
 
 // The table is read through the constant address space: it is written before
@@ -432,7 +435,7 @@ __device__ __forceinline__ FieldView field_view(const Queue &q, uint32_t f)
     f = __builtin_amdgcn_readfirstlane(f);
     ConstDesc *d = (ConstDesc *)q.fields + f;
     return FieldView{d->src, d->dst, d->flags, d->total, d->nx, d->ny, d->nbx, d->nby, d->nblocks, d->p0,
-                     d->payload, d->first, d->sel, d->rblocks, d->eps, d->eps_f};
+                     d->payload, d->first, d->sel, d->rblocks, d->eps, d->eps_f, d->cstride};
 }
 
 // Latch STATUS_* bits for the queue and, when per-field words exist, for
@@ -481,7 +484,7 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
         return;
     const FieldView a = field_view(q, s_field);
     const uint64_t b = t - a.first;
-    const uint32_t lane_off = (uint32_t)yq * a.nx + (uint32_t)x;  // element offset of (x, yq) in a z-plane
+    const uint32_t lane_off = ((uint32_t)yq * a.nx + (uint32_t)x) * a.cs;  // element offset of (x, yq) in a z-plane
 
     // load: for each z and r one coalesced row segment of N elements; the
     // rows of slab group g+1 stay in flight while group g is transformed
@@ -851,14 +854,15 @@ struct Big {
 // planes [0, n) of [0, n)^2, ZC planes at a time through LDS.  Rows are read
 // from src and written to dst (strides in elements; src may equal dst).
 template <typename T, int S, int n, int ZC, bool INV, int NT>
-__device__ __forceinline__ void xy_level(const T *src, size_t sps, size_t srs, T *dst, size_t dps, size_t drs, T *lds)
+__device__ __forceinline__ void xy_level(const T *src, size_t sps, size_t srs, uint32_t ses, T *dst, size_t dps,
+                                         size_t drs, T *lds)
 {
     constexpr int PX = n + 1, PS = n * PX;
     for (int z0 = 0; z0 < n; z0 += ZC) {
 #pragma unroll 8
         for (int e = threadIdx.x; e < ZC * n * n; e += NT) {
             const int x = e % n, y = (e / n) % n, j = e / (n * n);
-            lds[j * PS + y * PX + x] = src[(size_t)(z0 + j) * sps + (size_t)y * srs + x];
+            lds[j * PS + y * PX + x] = src[(size_t)(z0 + j) * sps + (size_t)y * srs + (size_t)x * ses];
         }
         lds_barrier();
         if constexpr (!INV) {
@@ -975,15 +979,15 @@ __device__ __forceinline__ void tail_levels(T *blk, T *lds)
 
 // Forward transform of a 64^3 block: field rows -> scratch slot.
 template <typename T, int S, int N, int NT>
-__device__ __forceinline__ void big_fwd(const T *src, size_t plane, size_t row, T *blk, T *lds)
+__device__ __forceinline__ void big_fwd(const T *src, size_t plane, size_t row, uint32_t cs, T *blk, T *lds)
 {
     using B = Big<T, N>;
-    xy_level<T, S, N, B::chunk(N), false, NT>(src, plane, row, blk, (size_t)N * N, N, lds);
+    xy_level<T, S, N, B::chunk(N), false, NT>(src, plane, row, cs, blk, (size_t)N * N, N, lds);
     gbarrier<NT>();
     z_level<T, S, N, N, false, NT>(blk);
     gbarrier<NT>();
     if constexpr (B::TAIL < N / 2) {
-        xy_level<T, S, N / 2, B::chunk(N / 2), false, NT>(blk, (size_t)N * N, N, blk, (size_t)N * N, N, lds);
+        xy_level<T, S, N / 2, B::chunk(N / 2), false, NT>(blk, (size_t)N * N, N, 1, blk, (size_t)N * N, N, lds);
         gbarrier<NT>();
         z_level<T, S, N, N / 2, false, NT>(blk);
         gbarrier<NT>();
@@ -1002,12 +1006,12 @@ __device__ __forceinline__ void big_inv(T *blk, T *dst, size_t plane, size_t row
     if constexpr (B::TAIL < N / 2) {
         z_level<T, S, N, N / 2, true, NT>(blk);
         gbarrier<NT>();
-        xy_level<T, S, N / 2, B::chunk(N / 2), true, NT>(blk, (size_t)N * N, N, blk, (size_t)N * N, N, lds);
+        xy_level<T, S, N / 2, B::chunk(N / 2), true, NT>(blk, (size_t)N * N, N, 1, blk, (size_t)N * N, N, lds);
         gbarrier<NT>();
     }
     z_level<T, S, N, N, true, NT>(blk);
     gbarrier<NT>();
-    xy_level<T, S, N, B::chunk(N), true, NT>(blk, (size_t)N * N, N, dst, plane, row, lds);
+    xy_level<T, S, N, B::chunk(N), true, NT>(blk, (size_t)N * N, N, 1, dst, plane, row, lds);
 }
 
 // Workgroup-wide exclusive scan of W word counts (W a multiple of NT): thread
@@ -1070,13 +1074,13 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
             break;
         const FieldView a = field_view(q, s_field);
         const uint64_t b = t - a.first;
-        const size_t plane = (size_t)a.nx * a.ny;
+        const size_t row = (size_t)a.nx * a.cs, plane = row * a.ny;
         const uint32_t bx = (uint32_t)(b % a.nbx);
         const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
         const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
-        const T *src = static_cast<const T *>(a.src) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+        const T *src = static_cast<const T *>(a.src) + ((size_t)bz * N * plane + (size_t)by * N * row + (size_t)bx * N * a.cs);
         bool bad = false;
-        big_fwd<T, S, N, NT>(src, plane, a.nx, blkS, lds);
+        big_fwd<T, S, N, NT>(src, plane, row, a.cs, blkS, lds);
 
         // decimation: wavefront w takes words w, w + WAVES, ...
         for (int w = wave; w < WORDS; w += WAVES) {
