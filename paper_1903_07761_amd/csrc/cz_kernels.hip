@@ -1236,10 +1236,10 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
 
 // ------------------------------------------------------------- bookkeeping
 
-// Reset the queue's ticket and status and publish an inline descriptor.
-// Forward: for every field (y index
-// of the grid) clear its look-back flags and write its header (payload size
-// 0 until its last block fills it), offset 0 and the zero pad between its
+// Reset the queue's ticket and status, publish an inline descriptor and
+// clear the per-field status words.  Forward: for every field (y index of
+// the grid) clear its look-back flags and write its header (payload size 0
+// until its last block fills it), offset 0 and the zero pad between its
 // offset table and payload; a field without blocks gets its total here.
 __global__ void prep_kernel(Queue q, int forward)
 {
