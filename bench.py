@@ -132,7 +132,8 @@ def zlib_ratio(stream_dev, nbytes: int, raw: int) -> float:
 
 def c2_sweep(codec, torch):
     """512^3 float32 bubble cloud, W4_li, 32^3 blocks: CR before / after zlib
-    (plain, byte-shuffled, and with Z4 / Z8 zeroing before the shuffle), PSNR
+    (plain, byte-shuffled, and with Z4 / Z8 zeroing before the shuffle; and
+    after the GPU Huffman stage over the shuffled stream), PSNR
     and max error for eps in {1e-2, 1e-3, 1e-4} of the range."""
     from paper_1903_07761_amd import fields as G
     from paper_1903_07761_amd import metrics
@@ -146,8 +147,10 @@ def c2_sweep(codec, torch):
         buf, n = codec.compress(f, 32, "W4_li", eps)
         rec = codec.decompress(buf, n)
         p, m = metrics.error_stats(f, rec)
+        sh = codec.shuffle(buf, n, 4)
         row = {"eps_frac": frac, "cr_stage1": round(raw / n, 3), "cr_zlib": round(zlib_ratio(buf, n, raw), 3),
-               "cr_shuffle_zlib": round(zlib_ratio(codec.shuffle(buf, n, 4), n, raw), 3),
+               "cr_shuffle_zlib": round(zlib_ratio(sh, n, raw), 3),
+               "cr_shuffle_huff": round(raw / codec.huff_encode(sh, n)[1], 3),
                "psnr_db": round(p, 2), "max_err": float(f"{m:.4g}")}
         # Z4 / Z8: zero the low mantissa bits of the detail coefficients, then shuffle
         for bits in (4, 8):
@@ -157,6 +160,52 @@ def c2_sweep(codec, torch):
             row[f"z{bits}"] = {"cr_shuffle_zlib": round(zlib_ratio(codec.shuffle(z, n, 4), n, raw), 3),
                                "psnr_db": round(pz, 2)}
         out.append(row)
+    return out
+
+
+def gpu_lossless(codec, torch, streams, sizes, raw, elems, reps: int = 3, host_sample: int = 256 << 20):
+    """The lossless substage on the GPU (byte shuffle, then canonical Huffman
+    in 16 KiB chunks): CR after it and its rates in stream bytes per second
+    (best of `reps`; encoding includes building the code on the host,
+    decoding the header read).  Every container is decoded and checked
+    against its input.  Beside it, host zlib (level 6, 4 MiB chunks, a thread
+    pool) on the first `host_sample` bytes of each shuffled stream, with the
+    GPU coder's container size on the same bytes."""
+    from paper_1903_07761_amd import lossless
+
+    out = {"cr_shuffle_huff": [], "huff_encode_GBps": [], "huff_decode_GBps": [],
+           "host_sample_bytes": [], "zlib_host_GBps": [], "huff_over_zlib_bytes": [],
+           "zlib_host_threads": min(16, os.cpu_count() or 1)}
+    for buf, n, r, e in zip(streams, sizes, raw, elems):
+        sh = codec.shuffle(buf, n, e)
+        t_enc, t_dec = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hb, hn = codec.huff_encode(sh, n)
+            t_enc.append(time.perf_counter() - t0)
+        back = torch.empty(max(n, 1), dtype=torch.uint8, device=sh.device)
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            codec.huff_decode(hb, hn, n, out=back)
+            torch.cuda.synchronize()
+            t_dec.append(time.perf_counter() - t0)
+        if codec.status() != 0 or not torch.equal(back[:n], sh[:n]):
+            raise SystemExit("GPU lossless stage: round trip failed")
+        del back, hb
+        k = min(n, host_sample)
+        host = sh[:k].cpu().numpy()
+        t0 = time.perf_counter()
+        z = lossless.deflate_chunks(memoryview(host))
+        t_zl = time.perf_counter() - t0
+        out["cr_shuffle_huff"].append(round(r / hn, 3))
+        out["huff_encode_GBps"].append(round(n / min(t_enc) / 1e9, 2))
+        out["huff_decode_GBps"].append(round(n / min(t_dec) / 1e9, 2))
+        out["host_sample_bytes"].append(k)
+        out["zlib_host_GBps"].append(round(k / t_zl / 1e9, 3))
+        out["huff_over_zlib_bytes"].append(round(codec.huff_encode(sh, k)[1] / lossless.container_bytes(z), 3))
+        del sh
     return out
 
 
@@ -563,6 +612,11 @@ def main():
         log("host zlib (CR after the lossless stage)")
         crz = [round(zlib_ratio(streams[i], sizes[i], raw[i]), 3) for i in range(len(items))]
 
+    gl = None
+    if not args.no_zlib:
+        log("GPU lossless stage beside host zlib")
+        gl = gpu_lossless(codec, torch, streams, sizes, raw, [t.element_size() for _, t, _, _, _ in items])
+
     log("copy bandwidth")
     copy_gbps = copy_bandwidth(torch)
 
@@ -602,6 +656,7 @@ def main():
         "max_err": maxerr,
         "cr_stage1": cr,
         "cr_zlib": crz,
+        "lossless_gpu": gl,
         "copy_GBps": round(copy_gbps, 1),
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),

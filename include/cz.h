@@ -232,6 +232,33 @@ int cz_shuffle(const void *d_in, size_t nbytes, uint32_t elem, void *d_out, void
 int cz_unshuffle(const void *d_in, size_t nbytes, uint32_t elem, void *d_out, void *stream);
 int cz_zero_details(cz_ctx *ctx, const cz_params *p, void *d_stream, size_t nbytes, uint32_t bits, void *stream);
 
+/* -------------------------------------------------------- GPU lossless stage
+ *
+ * Sec. 2.2-2.3: the second substage is a general-purpose lossless coder over
+ * the (optionally shuffled) output of the first.  This one runs on the GPU: a
+ * byte-oriented canonical Huffman code with lengths limited to 12 bits
+ * (package-merge over the byte histogram), over chunks of 16 KiB of input
+ * that decode independently.  Container "CZH1" (little-endian): 32-byte
+ * header {magic, u32 version 1, u64 raw bytes, u32 chunk bytes 16384,
+ * u32 chunks, u32 max length 12, u32 0}, 256 code lengths (u8), (chunks + 1)
+ * u64 chunk offsets relative to the payload, zero pad to 16 bytes, then each
+ * chunk's codes, bit-reversed and least significant bit first in little-endian
+ * 32-bit words, padded to a whole word.
+ *
+ * cz_huff_bound: worst-case container size for nbytes of input.
+ * cz_huff_encode: encode d_in[0, nbytes) into d_out (8-byte aligned, capacity out_cap >=
+ * cz_huff_bound, else CZ_ERR_CAPACITY with the bound in *h_out_bytes);
+ * synchronous (the code is built on the host from the histogram): returns
+ * the container size in *h_out_bytes.
+ * cz_huff_decode: decode the container d_in (8-byte aligned, in_bytes long) into d_out
+ * (4-byte aligned, out_cap >= raw bytes); reads the header synchronously,
+ * then asynchronous; a corrupt chunk latches CZ_ERR_FORMAT for
+ * cz_get_status.  Both use the context's workspace. */
+size_t cz_huff_bound(size_t nbytes);
+int cz_huff_encode(cz_ctx *ctx, const void *d_in, size_t nbytes, void *d_out, size_t out_cap, size_t *h_out_bytes,
+                   void *stream);
+int cz_huff_decode(cz_ctx *ctx, const void *d_in, size_t in_bytes, void *d_out, size_t out_cap, void *stream);
+
 /* ------------------------------------------------------------ random access
  *
  * Sec. 2.3 ("Data decompression"): decompression works block by block; a

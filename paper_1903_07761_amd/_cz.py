@@ -93,6 +93,12 @@ def lib() -> ctypes.CDLL:
         L.cz_unshuffle.restype = i32
         L.cz_zero_details.argtypes = [vp, P, vp, sz, u32, vp]
         L.cz_zero_details.restype = i32
+        L.cz_huff_bound.argtypes = [sz]
+        L.cz_huff_bound.restype = sz
+        L.cz_huff_encode.argtypes = [vp, vp, sz, vp, sz, PS, vp]
+        L.cz_huff_encode.restype = i32
+        L.cz_huff_decode.argtypes = [vp, vp, sz, vp, sz, vp]
+        L.cz_huff_decode.restype = i32
         PU32 = ctypes.POINTER(u32)
         L.cz_decompress_blocks.argtypes = [vp, P, vp, sz, PU32, sz, vp, sz, vp]
         L.cz_decompress_blocks.restype = i32
@@ -197,6 +203,16 @@ class Context:
         ids = _u32s(blocks)
         _check(lib().cz_decompress_blocks(self.handle, ctypes.byref(p), d_in, in_bytes, ids, len(blocks), d_out,
                                           out_cap, stream), "cz_decompress_blocks")
+
+    def huff_encode(self, d_in: int, nbytes: int, d_out: int, out_cap: int, stream: int = 0) -> int:
+        n = ctypes.c_size_t(0)
+        rc = lib().cz_huff_encode(self.handle, d_in, nbytes, d_out, out_cap, ctypes.byref(n), stream)
+        if rc != OK:
+            raise CzError(rc, "cz_huff_encode")
+        return n.value
+
+    def huff_decode(self, d_in: int, in_bytes: int, d_out: int, out_cap: int, stream: int = 0):
+        _check(lib().cz_huff_decode(self.handle, d_in, in_bytes, d_out, out_cap, stream), "cz_huff_decode")
 
     def zero_details(self, p: cz_params, d_stream: int, nbytes: int, bits: int, stream: int = 0):
         _check(lib().cz_zero_details(self.handle, ctypes.byref(p), d_stream, nbytes, bits, stream), "cz_zero_details")
@@ -389,3 +405,7 @@ class Cache:
             self.close()
         except Exception:
             pass
+
+
+def huff_bound(nbytes: int) -> int:
+    return int(lib().cz_huff_bound(nbytes))

@@ -158,5 +158,17 @@ class Codec:
                      out.numel() * out.element_size(), _stream_handle(buf.device))
         return out
 
+    def huff_encode(self, buf: torch.Tensor, nbytes: int):
+        """GPU lossless stage: returns (container buffer, size)."""
+        out = torch.empty(_cz.huff_bound(nbytes), dtype=torch.uint8, device=buf.device)
+        n = self.ctx.huff_encode(buf.data_ptr(), nbytes, out.data_ptr(), out.numel(), _stream_handle(buf.device))
+        return out, n
+
+    def huff_decode(self, buf: torch.Tensor, nbytes: int, raw_bytes: int, out: torch.Tensor | None = None):
+        if out is None:
+            out = torch.empty(max(raw_bytes, 1), dtype=torch.uint8, device=buf.device)
+        self.ctx.huff_decode(buf.data_ptr(), nbytes, out.data_ptr(), out.numel(), _stream_handle(buf.device))
+        return out
+
     def plan(self, op: str, ps) -> _cz.Plan:
         return _cz.Plan(self.ctx, op, ps)

@@ -367,7 +367,7 @@ int cz_create(cz_ctx **out, int device)
                     hipMemset(ctx->work, 0, sizeof(czk::CzWork)) == hipSuccess &&
                     hipHostMalloc(&ctx->pinned, sizeof(czk::CzWork), hipHostMallocDefault) == hipSuccess &&
                     ctx->flags.ensure(4096 * sizeof(uint64_t)) == CZ_OK && ctx->batch.init() == CZ_OK &&
-                    ctx->sel.init() == CZ_OK;
+                    ctx->sel.init() == CZ_OK && ctx->huff_stage.init() == CZ_OK;
     if (!ok) {
         cz_destroy(ctx);
         return CZ_ERR_HIP;
@@ -386,6 +386,8 @@ void cz_destroy(cz_ctx *ctx)
     ctx->scratch.release();
     ctx->batch.release();
     ctx->sel.release();
+    ctx->huff.release();
+    ctx->huff_stage.release();
     if (ctx->work)
         (void)hipFree(ctx->work);
     if (ctx->one)

@@ -254,6 +254,8 @@ struct cz_ctx {
     uint8_t variant[4][2][3] = {};  // tuned kernel variant per (N, precision, scheme)
     czh::BatchWork batch;                // batch calls
     czh::Staging sel;                    // selected-block decoding: (record, output block) pairs
+    czh::DevBuf huff;                    // lossless stage: histogram, code table, chunk sizes
+    czh::Staging huff_stage;             // lossless stage: header and code / decode tables
 };
 
 #endif  // CZ_HOST_H

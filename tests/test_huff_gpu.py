@@ -1,0 +1,163 @@
+"""GPU lossless stage (canonical Huffman over bytes, independently decodable
+chunks) against the oracle: containers byte-identical to the oracle's on the
+same input, the oracle's containers decoded to the input, and corrupt
+containers rejected."""
+import struct
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+CHUNK = 16384
+
+
+@pytest.fixture(scope="module")
+def codec():
+    need_gpu()
+    from paper_1903_07761_amd.codec import Codec
+
+    return Codec(0)
+
+
+def fib_bytes(seed):
+    """Fibonacci counts over 20 symbols: an unlimited Huffman code would need
+    19-bit codes, so the 12-bit limit is active."""
+    a, b, counts = 1, 1, []
+    for _ in range(20):
+        counts.append(a)
+        a, b = b, a + b
+    data = np.repeat(np.arange(20, dtype=np.uint8) * 13, counts)
+    return np.random.default_rng(seed).permutation(data)
+
+
+def shuffled_stream(codec, seed):
+    from paper_1903_07761_amd import fields
+
+    f = fields.bubble_cloud(64, seed, nbubbles=12, dtype=torch.float32).cuda()
+    eps = 1e-3 * float(f.max() - f.min())
+    buf, nb = codec.compress(f, 16, "W3_ai", eps)
+    sh = codec.shuffle(buf, nb, 4)
+    torch.cuda.synchronize()
+    return sh[:nb].cpu().numpy()
+
+
+def inputs(codec):
+    rng = np.random.default_rng(5)
+    yield "empty", np.zeros(0, np.uint8)
+    yield "one byte", np.array([200], np.uint8)
+    yield "one symbol", np.full(40000, 7, np.uint8)
+    yield "two symbols", rng.integers(0, 2, 3 * CHUNK + 1, dtype=np.uint8) * 255
+    yield "uniform ragged", rng.integers(0, 256, 3 * CHUNK + 777, dtype=np.uint8)
+    yield "geometric", np.minimum(rng.geometric(0.3, 2 * CHUNK + 5), 255).astype(np.uint8)
+    yield "fibonacci", fib_bytes(6)
+    yield "exact chunks", rng.integers(0, 64, 2 * CHUNK, dtype=np.uint8)
+    yield "shuffled stream", shuffled_stream(codec, 7)[: 6 * CHUNK + 123]
+
+
+def test_encode_matches_oracle(codec):
+    from oracle import huffman
+
+    for name, host in inputs(codec):
+        dev = torch.from_numpy(host.copy()).cuda()
+        out, n = codec.huff_encode(dev, host.size)
+        ref = huffman.encode(host.tobytes())
+        got = out[:n].cpu().numpy().tobytes()
+        assert n == len(ref), (name, n, len(ref))
+        assert got == ref, name
+        say(f"[huff] encode {name}: {host.size} -> {n} bytes ok")
+
+
+def test_decode_oracle_containers(codec):
+    from oracle import huffman
+
+    for name, host in inputs(codec):
+        blob = huffman.encode(host.tobytes())
+        dev = torch.frombuffer(bytearray(blob), dtype=torch.uint8).cuda()
+        out = codec.huff_decode(dev, len(blob), host.size)
+        torch.cuda.synchronize()
+        assert codec.status() == 0, name
+        assert out[: host.size].cpu().numpy().tobytes() == host.tobytes(), name
+        say(f"[huff] decode {name} ok")
+
+
+def test_large_round_trip_and_sampled_chunks(codec):
+    """8 MiB + 5 of a shuffled compressed stream pattern: the code lengths are
+    the oracle's for the histogram, sampled chunks are the oracle's encoding of
+    those 16 KiB, and decoding gives back every byte."""
+    from oracle import huffman
+
+    base = shuffled_stream(codec, 8)
+    reps = (8 * 2 ** 20 + 5 + base.size - 1) // base.size
+    host = np.tile(base, reps)[: 8 * 2 ** 20 + 5]
+    host[::4099] ^= 0x5A  # break the period
+    dev = torch.from_numpy(host).cuda()
+    out, n = codec.huff_encode(dev, host.size)
+    blob = out[:n].cpu().numpy().tobytes()
+    nchunks = (host.size + CHUNK - 1) // CHUNK
+    lengths = huffman.package_merge(np.bincount(host, minlength=256))
+    assert list(blob[32:288]) == lengths
+    codes = huffman.canonical_codes(lengths)
+    offs = struct.unpack_from(f"<{nchunks + 1}Q", blob, 288)
+    p0 = (288 + 8 * (nchunks + 1) + 15) // 16 * 16
+    assert p0 + offs[-1] == n
+    for k in (0, 1, nchunks // 2, nchunks - 2, nchunks - 1):
+        ref = huffman.encode_chunk(host[k * CHUNK:(k + 1) * CHUNK].tobytes(), codes)
+        assert blob[p0 + offs[k]:p0 + offs[k + 1]] == ref, k
+    back = codec.huff_decode(out, n, host.size)
+    torch.cuda.synchronize()
+    assert codec.status() == 0
+    assert torch.equal(back[: host.size], dev)
+    say(f"[huff] 8 MiB: ratio {host.size / n:.3f}")
+
+
+def test_huffman_errors(codec):
+    from oracle import huffman
+    from paper_1903_07761_amd import _cz
+
+    host = np.full(40000, 7, np.uint8)
+    dev = torch.from_numpy(host).cuda()
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(_cz.CzError) as e:
+        codec.ctx.huff_encode(dev.data_ptr(), host.size, small.data_ptr(), small.numel())
+    assert e.value.code == _cz.ERR_CAPACITY
+    blob = bytearray(huffman.encode(host.tobytes()))
+
+    def decode(b, nbytes=None, raw=host.size):
+        d = torch.frombuffer(bytearray(b), dtype=torch.uint8).cuda()
+        return codec.huff_decode(d, len(b) if nbytes is None else nbytes, raw)
+
+    bad = bytearray(blob)
+    bad[0:4] = b"XZH1"
+    with pytest.raises(_cz.CzError) as e:
+        decode(bad)
+    assert e.value.code == _cz.ERR_FORMAT
+    bad = bytearray(blob)
+    bad[32 + 3] = 1  # a second 1-bit code: Kraft sum 1.5 > 1
+    bad[32 + 7] = 1
+    bad[32 + 9] = 1
+    with pytest.raises(_cz.CzError) as e:
+        decode(bad)
+    assert e.value.code == _cz.ERR_FORMAT
+    with pytest.raises(_cz.CzError) as e:
+        decode(blob, raw=host.size - 1)  # output too small for the raw size
+    assert e.value.code == _cz.ERR_CAPACITY
+    # a payload bit pattern the single 1-bit code does not define
+    bad = bytearray(blob)
+    p0 = len(blob) - (struct.unpack_from("<Q", blob, 288 + 8 * 3)[0])
+    bad[p0] = 1
+    decode(bad)
+    torch.cuda.synchronize()
+    assert codec.status() == _cz.ERR_FORMAT
+    # the container cut short: the last chunk's words lie past its end
+    decode(blob, nbytes=len(blob) - 8)
+    torch.cuda.synchronize()
+    assert codec.status() == _cz.ERR_FORMAT
+    assert codec.status() == 0
+    # a valid container still decodes after the errors
+    out = decode(blob)
+    torch.cuda.synchronize()
+    assert codec.status() == 0 and out[: host.size].cpu().numpy().tobytes() == host.tobytes()
