@@ -39,7 +39,7 @@ def log(*a):
 def sources_sha() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1903_07761_amd", "csrc")
-    for name in ("cz_kernels.hip", "cz_kernels.h", "cz_lines.h"):  # the block kernels' sources
+    for name in ("cz_kernels.hip", "cz_kernels.h", "cz_lines.h", "cz_lookback.h"):  # the block kernels' sources
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode() + fh.read())
     return h.hexdigest()
@@ -165,7 +165,7 @@ def c2_sweep(codec, torch):
 
 def gpu_lossless(codec, torch, streams, sizes, raw, elems, reps: int = 3, host_sample: int = 256 << 20):
     """The lossless substage on the GPU (byte shuffle, then canonical Huffman
-    in 16 KiB chunks): CR after it and its rates in stream bytes per second
+    in 4 KiB chunks): CR after it and its rates in stream bytes per second
     (best of `reps`; encoding includes building the code on the host,
     decoding the header read).  Every container is decoded and checked
     against its input.  Beside it, host zlib (level 6, 4 MiB chunks, a thread

@@ -237,9 +237,9 @@ int cz_zero_details(cz_ctx *ctx, const cz_params *p, void *d_stream, size_t nbyt
  * Sec. 2.2-2.3: the second substage is a general-purpose lossless coder over
  * the (optionally shuffled) output of the first.  This one runs on the GPU: a
  * byte-oriented canonical Huffman code with lengths limited to 12 bits
- * (package-merge over the byte histogram), over chunks of 16 KiB of input
+ * (package-merge over the byte histogram), over chunks of 4 KiB of input
  * that decode independently.  Container "CZH1" (little-endian): 32-byte
- * header {magic, u32 version 1, u64 raw bytes, u32 chunk bytes 16384,
+ * header {magic, u32 version 1, u64 raw bytes, u32 chunk bytes 4096,
  * u32 chunks, u32 max length 12, u32 0}, 256 code lengths (u8), (chunks + 1)
  * u64 chunk offsets relative to the payload, zero pad to 16 bytes, then each
  * chunk's codes, bit-reversed and least significant bit first in little-endian

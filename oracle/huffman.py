@@ -34,7 +34,7 @@ import numpy as np
 
 MAGIC = b"CZH1"
 MAX_LEN = 12
-CHUNK = 16384
+CHUNK = 4096
 _HDR = struct.Struct("<4sIQIIII")  # 32 bytes
 
 

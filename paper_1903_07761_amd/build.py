@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcz.so")
 SOURCES = ["cz_kernels.hip", "cz_api.hip", "cz_server.hip", "cz_precond.hip", "cz_roi.hip", "cz_huff.hip"]
-HEADERS = ["cz_kernels.h", "cz_lines.h", "cz_host.h", os.path.join("..", "..", "include", "cz.h")]
+HEADERS = ["cz_kernels.h", "cz_lines.h", "cz_lookback.h", "cz_host.h", os.path.join("..", "..", "include", "cz.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

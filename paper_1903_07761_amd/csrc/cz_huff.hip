@@ -10,16 +10,17 @@
 // a leaf before a package of equal weight; the first 2n - 2 items give the
 // lengths).  Codes: canonical (RFC 1951, Sec. 3.2.2), written bit-reversed,
 // least significant bit first, into little-endian 32-bit words; each chunk of
-// 16 KiB of input is padded to whole words.  Container: 32-byte header
+// 4 KiB of input is padded to whole words.  Container: 32-byte header
 // {"CZH1", version 1, u64 raw bytes, u32 chunk bytes, u32 chunks, u32 max
 // length, u32 0}, 256 code lengths, (chunks + 1) u64 chunk offsets relative to
 // the payload, zero pad to 16 bytes, the chunks.
 //
 // Encoding: a histogram kernel, the code built on the host from the 256
-// counts, a kernel for each chunk's encoded size, a one-workgroup scan that
-// writes the offsets, and an encoding kernel (one workgroup a chunk, codes
-// packed with LDS atomics, the chunk copied out whole).  Decoding: one thread
-// a chunk with a 4096-entry lookup table in LDS.
+// counts, and one encoding kernel (one workgroup a chunk, codes packed with
+// LDS atomics, the chunk placed by a decoupled look-back over the chunk sizes
+// and copied out whole): two reads of the input.  Decoding: one thread
+// a chunk with a 4096-entry lookup table in LDS, the chunk's words read ahead
+// in 64-byte groups.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,12 +28,13 @@
 #include <vector>
 
 #include "cz_host.h"
+#include "cz_lookback.h"
 
 namespace {
 
 constexpr uint32_t MAGIC = 0x31485A43u;  // "CZH1"
 constexpr int MAXLEN = 12;
-constexpr uint32_t CHUNK = 16384;
+constexpr uint32_t CHUNK = 4096;
 constexpr int ENC_THREADS = 256;
 constexpr int BYTES_PER_THREAD = CHUNK / ENC_THREADS;
 constexpr uint32_t CHUNK_WORDS = (CHUNK * MAXLEN + 31) / 32;
@@ -40,94 +42,93 @@ constexpr size_t HEAD = 32 + 256;
 
 size_t payload_start(uint64_t nchunks) { return (HEAD + 8 * (nchunks + 1) + 15) & ~size_t(15); }
 
-__global__ __launch_bounds__(256) void hist_kernel(const uint8_t *__restrict__ in, uint64_t n,
-                                                   unsigned long long *hist)
-{
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
-        atomicAdd(&h[in[i]], 1u);
-    __syncthreads();
-    if (h[threadIdx.x])
-        atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
-}
+// Byte histogram.  Each workgroup counts into HIST_COPIES interleaved copies
+// of the 256 bins (lane l uses copy l % HIST_COPIES), so a run of equal bytes
+// -- the zero bytes of a shuffled stream -- spreads over several LDS words
+// instead of serializing on one.  The 16-byte-aligned middle of the input is
+// read 16 bytes a thread; the unaligned ends byte by byte.
+constexpr int HIST_THREADS = 256;
+constexpr int HIST_COPIES = 16;
 
-// Encoded bits of each chunk.
-__global__ __launch_bounds__(ENC_THREADS) void chunk_bits_kernel(const uint8_t *__restrict__ in, uint64_t n,
-                                                                 const uint32_t *__restrict__ code,
-                                                                 uint32_t *bits)
+__global__ __launch_bounds__(HIST_THREADS) void hist_kernel(const uint8_t *__restrict__ in, uint64_t n,
+                                                            unsigned long long *hist)
 {
-    __shared__ uint32_t s_len[256];
-    __shared__ uint32_t s_sum[ENC_THREADS / 64];
-    s_len[threadIdx.x] = code[threadIdx.x] >> 16;
+    __shared__ uint32_t h[256 * HIST_COPIES];
+    for (int k = threadIdx.x; k < 256 * HIST_COPIES; k += HIST_THREADS)
+        h[k] = 0;
     __syncthreads();
-    const uint64_t c = blockIdx.x;
-    const uint64_t base = c * CHUNK;
-    const uint64_t end = min(n, base + CHUNK);
-    uint32_t sum = 0;
-    for (uint64_t i = base + threadIdx.x; i < end; i += ENC_THREADS)
-        sum += s_len[in[i]];
-    for (int o = 32; o > 0; o >>= 1)
-        sum += __shfl_xor(sum, o);
-    if (threadIdx.x % 64 == 0)
-        s_sum[threadIdx.x / 64] = sum;
+    const uint32_t copy = threadIdx.x % HIST_COPIES;
+    const uint64_t head = min<uint64_t>(n, (16 - (reinterpret_cast<uintptr_t>(in) & 15)) & 15);
+    const uint64_t units = (n - head) / 16;
+    const uint64_t tail = head + units * 16;
+    const uint64_t gid = (uint64_t)blockIdx.x * HIST_THREADS + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * HIST_THREADS;
+    const uint4 *mid = reinterpret_cast<const uint4 *>(in + head);
+    for (uint64_t u = gid; u < units; u += stride) {
+        const uint4 v = mid[u];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            atomicAdd(&h[((w[k / 4] >> (8 * (k % 4))) & 0xFFu) * HIST_COPIES + copy], 1u);
+    }
+    // the unaligned head and the tail: at most 15 bytes each
+    if (gid < head)
+        atomicAdd(&h[in[gid] * HIST_COPIES + copy], 1u);
+    if (gid < n - tail)
+        atomicAdd(&h[in[tail + gid] * HIST_COPIES + copy], 1u);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    for (int bin = threadIdx.x; bin < 256; bin += HIST_THREADS) {
         uint32_t t = 0;
-        for (int w = 0; w < ENC_THREADS / 64; ++w)
-            t += s_sum[w];
-        bits[c] = t;
+#pragma unroll
+        for (int k = 0; k < HIST_COPIES; ++k)
+            t += h[bin * HIST_COPIES + k];
+        if (t)
+            atomicAdd(&hist[bin], (unsigned long long)t);
     }
 }
 
-// Chunk offsets (bytes, whole words) into the container, and the payload size.
-__global__ __launch_bounds__(1024) void scan_kernel(const uint32_t *__restrict__ bits, uint64_t nchunks,
-                                                    uint64_t *offs, uint64_t *total)
-{
-    __shared__ uint64_t s_part[1024];
-    const uint64_t per = (nchunks + 1023) / 1024;
-    const uint64_t b0 = threadIdx.x * per, b1 = min(nchunks, b0 + per);
-    uint64_t sum = 0;
-    for (uint64_t c = b0; c < b1; ++c)
-        sum += (uint64_t)((bits[c] + 31) / 32) * 4;
-    s_part[threadIdx.x] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t run = 0;
-        for (int t = 0; t < 1024; ++t) {
-            const uint64_t v = s_part[t];
-            s_part[t] = run;
-            run += v;
-        }
-        *total = run;
-        offs[nchunks] = run;
-    }
-    __syncthreads();
-    uint64_t run = s_part[threadIdx.x];
-    for (uint64_t c = b0; c < b1; ++c) {
-        offs[c] = run;
-        run += (uint64_t)((bits[c] + 31) / 32) * 4;
-    }
-}
-
+// One workgroup a chunk, in ticket order: each thread codes 16 consecutive
+// bytes; a workgroup scan of the threads' bit counts places every code in the
+// chunk's words, packed in LDS with atomic ORs; the chunk's byte size goes
+// through a decoupled look-back over the chunks (the same single-pass
+// exclusive scan that places the block records), which gives its offset in
+// the payload; the chunk is then copied out whole.
 __global__ __launch_bounds__(ENC_THREADS) void encode_kernel(const uint8_t *__restrict__ in, uint64_t n,
-                                                             const uint32_t *__restrict__ code,
-                                                             const uint64_t *__restrict__ offs, uint8_t *payload)
+                                                             const uint32_t *__restrict__ code, uint64_t nchunks,
+                                                             uint64_t *flags, uint32_t *ticket, uint64_t *offs,
+                                                             uint8_t *payload, uint64_t *total, uint32_t *status)
 {
     __shared__ uint32_t s_code[256];
     __shared__ uint32_t s_words[CHUNK_WORDS];
     __shared__ uint32_t s_scan[ENC_THREADS / 64 + 1];
+    __shared__ uint64_t s_c, s_off;
+    if (threadIdx.x == 0)
+        s_c = atomicAdd(ticket, 1u);
     s_code[threadIdx.x] = code[threadIdx.x];
     for (uint32_t w = threadIdx.x; w < CHUNK_WORDS; w += ENC_THREADS)
         s_words[w] = 0;
     __syncthreads();
-    const uint64_t c = blockIdx.x;
+    const uint64_t c = s_c;
+    if (c >= nchunks)
+        return;
     const uint64_t base = c * CHUNK + (uint64_t)threadIdx.x * BYTES_PER_THREAD;
     const int cnt = (int)min<uint64_t>(BYTES_PER_THREAD, base < n ? n - base : 0);
+    uint8_t b[BYTES_PER_THREAD];
+    if (cnt == BYTES_PER_THREAD && (reinterpret_cast<uintptr_t>(in + base) & 15) == 0) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(in + base);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < BYTES_PER_THREAD; ++k)
+            b[k] = (uint8_t)(w[k / 4] >> (8 * (k % 4)));
+    } else {
+#pragma unroll
+        for (int k = 0; k < BYTES_PER_THREAD; ++k)
+            b[k] = k < cnt ? in[base + k] : 0;
+    }
     uint32_t mybits = 0;
-    for (int i = 0; i < cnt; ++i)
-        mybits += s_code[in[base + i]] >> 16;
+#pragma unroll
+    for (int k = 0; k < BYTES_PER_THREAD; ++k)
+        mybits += k < cnt ? s_code[b[k]] >> 16 : 0u;
     // exclusive scan of the threads' bit counts
     const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     uint32_t incl = mybits;
@@ -150,32 +151,60 @@ __global__ __launch_bounds__(ENC_THREADS) void encode_kernel(const uint8_t *__re
     }
     __syncthreads();
     uint32_t pos = s_scan[wave] + incl - mybits;
-    for (int i = 0; i < cnt; ++i) {
-        const uint32_t e = s_code[in[base + i]];
-        const uint32_t l = e >> 16, r = e & 0xFFFFu;
-        const uint32_t w = pos / 32, sh = pos % 32;
-        atomicOr(&s_words[w], r << sh);
-        if (sh + l > 32)
-            atomicOr(&s_words[w + 1], r >> (32 - sh));
-        pos += l;
+#pragma unroll
+    for (int k = 0; k < BYTES_PER_THREAD; ++k) {
+        if (k < cnt) {
+            const uint32_t e = s_code[b[k]];
+            const uint32_t l = e >> 16, r = e & 0xFFFFu;
+            const uint32_t w = pos / 32, sh = pos % 32;
+            atomicOr(&s_words[w], r << sh);
+            if (sh + l > 32)
+                atomicOr(&s_words[w + 1], r >> (32 - sh));
+            pos += l;
+        }
+    }
+    const uint32_t words = (s_scan[ENC_THREADS / 64] + 31) / 32;
+    const uint64_t bytes = (uint64_t)words * 4;
+    if (threadIdx.x < 64) {
+        const uint64_t o = czk::lookback_wave(flags, c, bytes, status, nullptr);
+        if (threadIdx.x == 0)
+            s_off = o;
     }
     __syncthreads();
-    const uint32_t words = (s_scan[ENC_THREADS / 64] + 31) / 32;
-    uint32_t *dst = reinterpret_cast<uint32_t *>(payload + offs[c]);
+    const uint64_t off = s_off;
+    if (threadIdx.x == 0) {
+        if (c == 0)
+            offs[0] = 0;
+        offs[c + 1] = off + bytes;
+        if (c + 1 == nchunks)
+            *total = off + bytes;
+    }
+    uint32_t *dst = reinterpret_cast<uint32_t *>(payload + off);
     for (uint32_t w = threadIdx.x; w < words; w += ENC_THREADS)
         dst[w] = s_words[w];
 }
 
 // One thread a chunk; table[k] = symbol | length << 8 for the next 12 bits k.
-__global__ __launch_bounds__(64) void decode_kernel(const uint8_t *__restrict__ payload, uint64_t payload_bytes,
-                                                    const uint64_t *__restrict__ offs, const uint16_t *__restrict__ table,
-                                                    uint64_t nchunks, uint64_t raw, uint8_t *out, uint32_t *status)
+// A thread reads its chunk in groups of GW words, the next group in flight
+// while the current one is decoded (a word at a time into a 64-bit window),
+// so a refill rarely waits for memory.  Words past the chunk's end are read
+// (clamped to the payload) but never decoded from: a prefix code decides each
+// symbol by its own bits, and the bits a chunk's symbols use must lie within
+// its words.
+constexpr int DEC_THREADS = 64;  // small workgroups: a short stream has few chunks
+constexpr int GW = 16;
+
+__global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__restrict__ payload,
+                                                             uint64_t payload_bytes,
+                                                             const uint64_t *__restrict__ offs,
+                                                             const uint16_t *__restrict__ table, uint64_t nchunks,
+                                                             uint64_t raw, uint8_t *out, uint32_t *status)
 {
     __shared__ uint16_t s_tab[1u << MAXLEN];
-    for (uint32_t k = threadIdx.x; k < (1u << MAXLEN); k += 64)
+    for (uint32_t k = threadIdx.x; k < (1u << MAXLEN); k += DEC_THREADS)
         s_tab[k] = table[k];
     __syncthreads();
-    const uint64_t c = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+    const uint64_t c = (uint64_t)blockIdx.x * DEC_THREADS + threadIdx.x;
     if (c >= nchunks)
         return;
     const uint64_t o0 = offs[c], o1 = offs[c + 1];
@@ -183,40 +212,63 @@ __global__ __launch_bounds__(64) void decode_kernel(const uint8_t *__restrict__ 
         atomicOr(status, czk::STATUS_FORMAT);
         return;
     }
-    const uint32_t *w = reinterpret_cast<const uint32_t *>(payload + o0);
-    const uint64_t nwords = (o1 - o0) / 4;
     const uint64_t start = c * CHUNK;
-    const uint32_t n = (uint32_t)min<uint64_t>(CHUNK, raw - start);
-    uint64_t window = 0;  // the next bits, lowest first
-    uint32_t avail = 0;
-    uint64_t next = 0, used = 0;
-    uint32_t pack = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        if (avail < MAXLEN) {
-            const uint64_t v = next < nwords ? w[next] : 0u;  // zeros past the chunk's words
-            ++next;
-            window |= v << avail;
-            avail += 32;
-        }
-        const uint16_t e = s_tab[window & ((1u << MAXLEN) - 1)];
-        const uint32_t l = e >> 8;
-        used += l;
-        if (l == 0 || used > nwords * 32) {  // no such code, or the chunk's bits ran out
-            atomicOr(status, czk::STATUS_FORMAT);
-            return;
-        }
-        window >>= l;
-        avail -= l;
-        pack |= (uint32_t)(e & 0xFF) << (8 * (i % 4));
-        if (i % 4 == 3 || i + 1 == n) {
-            if (i % 4 == 3)
-                *reinterpret_cast<uint32_t *>(out + start + i - 3) = pack;
-            else
-                for (uint32_t k = 0; k <= i % 4; ++k)
-                    out[start + i - i % 4 + k] = (uint8_t)(pack >> (8 * k));
-            pack = 0;
-        }
+    const uint32_t n = (uint32_t)min<uint64_t>(CHUNK, raw - start);  // >= 1 for c < nchunks
+    if (o1 == o0) {
+        atomicOr(status, czk::STATUS_FORMAT);  // symbols but no bits
+        return;
     }
+    const uint32_t *pw = reinterpret_cast<const uint32_t *>(payload);
+    const uint64_t last = payload_bytes / 4 - 1;  // payload_bytes >= o1 >= 4
+    const uint64_t w0 = o0 / 4;
+    const uint64_t nbits = (o1 - o0) * 8;
+    uint32_t cur[GW], nxt[GW];
+#pragma unroll
+    for (int k = 0; k < GW; ++k)
+        cur[k] = pw[min(w0 + k, last)];
+#pragma unroll
+    for (int k = 0; k < GW; ++k)
+        nxt[k] = pw[min(w0 + GW + k, last)];
+    uint64_t window = 0, used = 0, g = 0;
+    uint32_t avail = 0, i = 0, pack = 0;
+    uint32_t *o32 = reinterpret_cast<uint32_t *>(out + start);
+    while (i < n) {
+#pragma unroll
+        for (int k = 0; k < GW; ++k) {
+            if (i >= n)
+                break;
+            window |= (uint64_t)cur[k] << avail;  // avail < MAXLEN here
+            avail += 32;
+            while (avail >= (uint32_t)MAXLEN && i < n) {
+                const uint16_t e = s_tab[window & ((1u << MAXLEN) - 1)];
+                const uint32_t l = e >> 8;
+                used += l;
+                if (l == 0 || used > nbits) {  // no such code, or past the chunk's bits
+                    atomicOr(status, czk::STATUS_FORMAT);
+                    return;
+                }
+                window >>= l;
+                avail -= l;
+                pack |= (uint32_t)(e & 0xFF) << (8 * (i % 4));
+                if (i % 4 == 3) {
+                    o32[i / 4] = pack;
+                    pack = 0;
+                }
+                ++i;
+            }
+        }
+        // the next group becomes current; the one after it is requested
+        ++g;
+#pragma unroll
+        for (int k = 0; k < GW; ++k)
+            cur[k] = nxt[k];
+#pragma unroll
+        for (int k = 0; k < GW; ++k)
+            nxt[k] = pw[min(w0 + (g + 1) * GW + k, last)];
+    }
+    if (n % 4)
+        for (uint32_t k = 0; k < n % 4; ++k)
+            out[start + n - n % 4 + k] = (uint8_t)(pack >> (8 * k));
 }
 
 // Package-merge: length-limited optimal code lengths (see the file header).
@@ -328,23 +380,22 @@ int cz_huff_encode(cz_ctx *ctx, const void *d_in, size_t nbytes, void *d_out, si
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint8_t *in = static_cast<const uint8_t *>(d_in);
     uint8_t *out = static_cast<uint8_t *>(d_out);
-    // workspace: histogram (256 u64), code table (256 u32), chunk bits, payload size
-    const size_t bits_bytes = (nchunks * 4 + 7) & ~uint64_t(7);
-    const size_t ws = 256 * 8 + 256 * 4 + bits_bytes + 8;
-    int rc = ctx->huff.ensure(ws);
+    // workspace: histogram (256 u64), code table (256 u32), ticket, status,
+    // payload size, then the look-back flags (one u64 a chunk)
+    constexpr size_t W_HIST = 0, W_CODE = 2048, W_TICKET = 3072, W_STATUS = 3076, W_TOTAL = 3080, W_FLAGS = 3088;
+    int rc = ctx->huff.ensure(W_FLAGS + nchunks * 8);
     if (rc != CZ_OK)
         return rc;
     uint8_t *w = static_cast<uint8_t *>(ctx->huff.ptr);
-    unsigned long long *hist = reinterpret_cast<unsigned long long *>(w);
-    uint32_t *code = reinterpret_cast<uint32_t *>(w + 2048);
-    uint32_t *bits = reinterpret_cast<uint32_t *>(w + 3072);
-    uint64_t *total = reinterpret_cast<uint64_t *>(w + 3072 + bits_bytes);
+    unsigned long long *hist = reinterpret_cast<unsigned long long *>(w + W_HIST);
+    uint32_t *code = reinterpret_cast<uint32_t *>(w + W_CODE);
+    uint64_t *total = reinterpret_cast<uint64_t *>(w + W_TOTAL);
     uint64_t counts[256] = {0};
     if (hipMemsetAsync(hist, 0, 2048, st) != hipSuccess)
         return CZ_ERR_HIP;
     if (nbytes) {
-        const int g = (int)std::min<uint64_t>((nbytes + 255) / 256, 8192);
-        hipLaunchKernelGGL(hist_kernel, dim3(g), dim3(256), 0, st, in, (uint64_t)nbytes, hist);
+        const int g = (int)std::min<uint64_t>((nbytes / 16 + HIST_THREADS - 1) / HIST_THREADS + 1, 4096);
+        hipLaunchKernelGGL(hist_kernel, dim3(g), dim3(HIST_THREADS), 0, st, in, (uint64_t)nbytes, hist);
         if (hipGetLastError() != hipSuccess)
             return CZ_ERR_HIP;
     }
@@ -361,7 +412,8 @@ int cz_huff_encode(cz_ctx *ctx, const void *d_in, size_t nbytes, void *d_out, si
                              (uint32_t)MAXLEN, 0};
     std::memcpy(head, h32, 32);
     const size_t p0 = payload_start(nchunks);
-    // header + code table through pinned staging; the pad between offsets and payload zeroed
+    // header + code table through pinned staging; the pad between offsets and
+    // payload, the ticket, status and total, and the flags start at zero
     std::vector<uint8_t> stage(HEAD + 1024);
     std::memcpy(stage.data(), head, HEAD);
     std::memcpy(stage.data() + HEAD, table, 1024);
@@ -370,25 +422,27 @@ int cz_huff_encode(cz_ctx *ctx, const void *d_in, size_t nbytes, void *d_out, si
     const uint8_t *staged = static_cast<const uint8_t *>(ctx->huff_stage.dev.ptr);
     if (hipMemcpyAsync(out, staged, HEAD, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(code, staged + HEAD, 1024, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-        hipMemsetAsync(out + HEAD + 8 * (nchunks + 1), 0, p0 - (HEAD + 8 * (nchunks + 1)), st) != hipSuccess)
+        hipMemsetAsync(out + HEAD + 8 * (nchunks + 1), 0, p0 - (HEAD + 8 * (nchunks + 1)), st) != hipSuccess ||
+        hipMemsetAsync(w + W_TICKET, 0, W_FLAGS - W_TICKET + nchunks * 8, st) != hipSuccess)
         return CZ_ERR_HIP;
     uint64_t *offs = reinterpret_cast<uint64_t *>(out + HEAD);
     if (nchunks) {
-        hipLaunchKernelGGL(chunk_bits_kernel, dim3((unsigned)nchunks), dim3(ENC_THREADS), 0, st, in, (uint64_t)nbytes,
-                           code, bits);
-        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, bits, nchunks, offs, total);
         hipLaunchKernelGGL(encode_kernel, dim3((unsigned)nchunks), dim3(ENC_THREADS), 0, st, in, (uint64_t)nbytes,
-                           code, offs, out + p0);
+                           code, nchunks, reinterpret_cast<uint64_t *>(w + W_FLAGS),
+                           reinterpret_cast<uint32_t *>(w + W_TICKET), offs, out + p0, total,
+                           reinterpret_cast<uint32_t *>(w + W_STATUS));
         if (hipGetLastError() != hipSuccess)
             return CZ_ERR_HIP;
-    } else if (hipMemsetAsync(offs, 0, 8, st) != hipSuccess || hipMemsetAsync(total, 0, 8, st) != hipSuccess) {
+    } else if (hipMemsetAsync(offs, 0, 8, st) != hipSuccess) {
         return CZ_ERR_HIP;
     }
-    uint64_t payload = 0;
-    if (hipMemcpyAsync(&payload, total, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+    uint64_t back[2] = {0, 0};  // status word (low half), payload size
+    if (hipMemcpyAsync(back, w + W_TICKET, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return CZ_ERR_HIP;
-    *h_out_bytes = p0 + payload;
+    if ((uint32_t)(back[0] >> 32) != 0)
+        return CZ_ERR_TIMEOUT;
+    *h_out_bytes = p0 + back[1];
     return CZ_OK;
 }
 
@@ -446,8 +500,8 @@ int cz_huff_decode(cz_ctx *ctx, const void *d_in, size_t in_bytes, void *d_out, 
     if (rc != CZ_OK)
         return rc;
     const uint8_t *in = static_cast<const uint8_t *>(d_in);
-    const unsigned g = (unsigned)((nchunks + 63) / 64);
-    hipLaunchKernelGGL(decode_kernel, dim3(g), dim3(64), 0, st, in + p0, (uint64_t)(in_bytes - p0),
+    const unsigned g = (unsigned)((nchunks + DEC_THREADS - 1) / DEC_THREADS);
+    hipLaunchKernelGGL(decode_kernel, dim3(g), dim3(DEC_THREADS), 0, st, in + p0, (uint64_t)(in_bytes - p0),
                        reinterpret_cast<const uint64_t *>(in + HEAD),
                        static_cast<const uint16_t *>(ctx->huff_stage.dev.ptr), nchunks, raw,
                        static_cast<uint8_t *>(d_out), &ctx->work->status);

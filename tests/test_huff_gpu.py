@@ -12,7 +12,7 @@ from gpu_common import need_gpu, say
 
 pytestmark = pytest.mark.gpu
 
-CHUNK = 16384
+CHUNK = 4096
 
 
 @pytest.fixture(scope="module")
@@ -87,7 +87,7 @@ def test_decode_oracle_containers(codec):
 def test_large_round_trip_and_sampled_chunks(codec):
     """8 MiB + 5 of a shuffled compressed stream pattern: the code lengths are
     the oracle's for the histogram, sampled chunks are the oracle's encoding of
-    those 16 KiB, and decoding gives back every byte."""
+    those 4 KiB, and decoding gives back every byte."""
     from oracle import huffman
 
     base = shuffled_stream(codec, 8)
@@ -147,7 +147,8 @@ def test_huffman_errors(codec):
     assert e.value.code == _cz.ERR_CAPACITY
     # a payload bit pattern the single 1-bit code does not define
     bad = bytearray(blob)
-    p0 = len(blob) - (struct.unpack_from("<Q", blob, 288 + 8 * 3)[0])
+    nchunks = (host.size + CHUNK - 1) // CHUNK
+    p0 = len(blob) - struct.unpack_from("<Q", blob, 288 + 8 * nchunks)[0]
     bad[p0] = 1
     decode(bad)
     torch.cuda.synchronize()
