@@ -250,7 +250,7 @@ int cz_zero_details(cz_ctx *ctx, const cz_params *p, void *d_stream, size_t nbyt
  * cz_huff_bound, else CZ_ERR_CAPACITY with the bound in *h_out_bytes);
  * synchronous (the code is built on the host from the histogram): returns
  * the container size in *h_out_bytes.
- * cz_huff_decode: decode the container d_in (8-byte aligned, in_bytes long) into d_out
+ * cz_huff_decode: decode the container d_in (16-byte aligned, in_bytes long) into d_out
  * (4-byte aligned, out_cap >= raw bytes); reads the header synchronously,
  * then asynchronous; a corrupt chunk latches CZ_ERR_FORMAT for
  * cz_get_status.  Both use the context's workspace. */

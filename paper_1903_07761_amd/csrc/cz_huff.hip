@@ -16,11 +16,11 @@
 // the payload, zero pad to 16 bytes, the chunks.
 //
 // Encoding: a histogram kernel, the code built on the host from the 256
-// counts, and one encoding kernel (one workgroup a chunk, codes packed with
-// LDS atomics, the chunk placed by a decoupled look-back over the chunk sizes
-// and copied out whole): two reads of the input.  Decoding: one thread
-// a chunk with a 4096-entry lookup table in LDS, the chunk's words read ahead
-// in 64-byte groups.
+// counts, and one encoding kernel (one workgroup a group of chunks, codes
+// packed with LDS atomics, the group placed by a decoupled look-back over the
+// group sizes and copied out whole): two reads of the input.  Decoding: one thread
+// a chunk with a 4096-entry lookup table in LDS, the chunk's words read
+// ahead in 16-byte blocks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -87,112 +87,152 @@ __global__ __launch_bounds__(HIST_THREADS) void hist_kernel(const uint8_t *__res
     }
 }
 
-// One workgroup a chunk, in ticket order: each thread codes 16 consecutive
-// bytes; a workgroup scan of the threads' bit counts places every code in the
-// chunk's words, packed in LDS with atomic ORs; the chunk's byte size goes
-// through a decoupled look-back over the chunks (the same single-pass
-// exclusive scan that places the block records), which gives its offset in
-// the payload; the chunk is then copied out whole.
+// One workgroup a group of CPG consecutive chunks, groups in ticket order.
+// Thread t codes bytes [16 t, 16 t + 16) of every chunk of the group; a
+// workgroup scan of the threads' bit counts (one per chunk) places every code
+// in its chunk's words, packed in LDS with atomic ORs.  The group's byte size
+// goes through a decoupled look-back over the groups (the same single-pass
+// exclusive scan that places the block records), which gives the group's
+// offset in the payload; its chunks are then copied out whole, back to back.
+constexpr int CPG = 8;
+
 __global__ __launch_bounds__(ENC_THREADS) void encode_kernel(const uint8_t *__restrict__ in, uint64_t n,
                                                              const uint32_t *__restrict__ code, uint64_t nchunks,
                                                              uint64_t *flags, uint32_t *ticket, uint64_t *offs,
                                                              uint8_t *payload, uint64_t *total, uint32_t *status)
 {
+    constexpr int NW = ENC_THREADS / 64;
     __shared__ uint32_t s_code[256];
-    __shared__ uint32_t s_words[CHUNK_WORDS];
-    __shared__ uint32_t s_scan[ENC_THREADS / 64 + 1];
-    __shared__ uint64_t s_c, s_off;
+    __shared__ uint32_t s_words[CPG][CHUNK_WORDS];
+    __shared__ uint32_t s_scan[CPG][NW + 1];  // per chunk: wave prefixes, then the chunk's bits
+    __shared__ uint32_t s_cw[CPG + 1];        // word offsets of the chunks within the group
+    __shared__ uint64_t s_g, s_off;
     if (threadIdx.x == 0)
-        s_c = atomicAdd(ticket, 1u);
+        s_g = atomicAdd(ticket, 1u);
     s_code[threadIdx.x] = code[threadIdx.x];
-    for (uint32_t w = threadIdx.x; w < CHUNK_WORDS; w += ENC_THREADS)
-        s_words[w] = 0;
+    for (uint32_t w = threadIdx.x; w < CPG * CHUNK_WORDS; w += ENC_THREADS)
+        (&s_words[0][0])[w] = 0;
     __syncthreads();
-    const uint64_t c = s_c;
-    if (c >= nchunks)
+    const uint64_t g = s_g;
+    const uint64_t c0 = g * CPG;
+    if (c0 >= nchunks)
         return;
-    const uint64_t base = c * CHUNK + (uint64_t)threadIdx.x * BYTES_PER_THREAD;
-    const int cnt = (int)min<uint64_t>(BYTES_PER_THREAD, base < n ? n - base : 0);
-    uint8_t b[BYTES_PER_THREAD];
-    if (cnt == BYTES_PER_THREAD && (reinterpret_cast<uintptr_t>(in + base) & 15) == 0) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(in + base);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int k = 0; k < BYTES_PER_THREAD; ++k)
-            b[k] = (uint8_t)(w[k / 4] >> (8 * (k % 4)));
-    } else {
-#pragma unroll
-        for (int k = 0; k < BYTES_PER_THREAD; ++k)
-            b[k] = k < cnt ? in[base + k] : 0;
-    }
-    uint32_t mybits = 0;
-#pragma unroll
-    for (int k = 0; k < BYTES_PER_THREAD; ++k)
-        mybits += k < cnt ? s_code[b[k]] >> 16 : 0u;
-    // exclusive scan of the threads' bit counts
+    const int nc = (int)min<uint64_t>(CPG, nchunks - c0);
     const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    uint32_t incl = mybits;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t v = __shfl_up(incl, o);
-        if (lane >= (uint32_t)o)
-            incl += v;
+    uint32_t data[CPG][4];
+    int cnt[CPG];
+    uint32_t mybits[CPG], incl[CPG];
+#pragma unroll
+    for (int j = 0; j < CPG; ++j) {
+        const uint64_t base = (c0 + j) * CHUNK + (uint64_t)threadIdx.x * BYTES_PER_THREAD;
+        cnt[j] = j < nc ? (int)min<uint64_t>(BYTES_PER_THREAD, base < n ? n - base : 0) : 0;
+        if (cnt[j] == BYTES_PER_THREAD && (reinterpret_cast<uintptr_t>(in + base) & 15) == 0) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(in + base);
+            data[j][0] = v.x;
+            data[j][1] = v.y;
+            data[j][2] = v.z;
+            data[j][3] = v.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t w = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    w |= (4 * q + k < cnt[j] ? (uint32_t)in[base + 4 * q + k] : 0u) << (8 * k);
+                data[j][q] = w;
+            }
+        }
+        uint32_t bits = 0;
+#pragma unroll
+        for (int k = 0; k < BYTES_PER_THREAD; ++k)
+            bits += k < cnt[j] ? s_code[(data[j][k / 4] >> (8 * (k % 4))) & 0xFFu] >> 16 : 0u;
+        mybits[j] = bits;
+        incl[j] = bits;
     }
-    if (lane == 63)
-        s_scan[wave] = incl;
+    // exclusive scans of the threads' bit counts, one per chunk
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int j = 0; j < CPG; ++j) {
+            const uint32_t v = __shfl_up(incl[j], o);
+            if (lane >= (uint32_t)o)
+                incl[j] += v;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int j = 0; j < CPG; ++j)
+            s_scan[j][wave] = incl[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < CPG) {
+        const int j = threadIdx.x;
+        uint32_t run = 0;
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t v = s_scan[j][w];
+            s_scan[j][w] = run;
+            run += v;
+        }
+        s_scan[j][NW] = run;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t run = 0;
-        for (int w = 0; w < ENC_THREADS / 64; ++w) {
-            const uint32_t v = s_scan[w];
-            s_scan[w] = run;
-            run += v;
+        for (int j = 0; j < CPG; ++j) {
+            s_cw[j] = run;
+            run += (s_scan[j][NW] + 31) / 32;
         }
-        s_scan[ENC_THREADS / 64] = run;
+        s_cw[CPG] = run;
+    }
+#pragma unroll
+    for (int j = 0; j < CPG; ++j) {
+        uint32_t pos = s_scan[j][wave] + incl[j] - mybits[j];
+#pragma unroll
+        for (int k = 0; k < BYTES_PER_THREAD; ++k) {
+            if (k < cnt[j]) {
+                const uint32_t e = s_code[(data[j][k / 4] >> (8 * (k % 4))) & 0xFFu];
+                const uint32_t l = e >> 16, r = e & 0xFFFFu;
+                const uint32_t w = pos / 32, sh = pos % 32;
+                atomicOr(&s_words[j][w], r << sh);
+                if (sh + l > 32)
+                    atomicOr(&s_words[j][w + 1], r >> (32 - sh));
+                pos += l;
+            }
+        }
     }
     __syncthreads();
-    uint32_t pos = s_scan[wave] + incl - mybits;
-#pragma unroll
-    for (int k = 0; k < BYTES_PER_THREAD; ++k) {
-        if (k < cnt) {
-            const uint32_t e = s_code[b[k]];
-            const uint32_t l = e >> 16, r = e & 0xFFFFu;
-            const uint32_t w = pos / 32, sh = pos % 32;
-            atomicOr(&s_words[w], r << sh);
-            if (sh + l > 32)
-                atomicOr(&s_words[w + 1], r >> (32 - sh));
-            pos += l;
-        }
-    }
-    const uint32_t words = (s_scan[ENC_THREADS / 64] + 31) / 32;
-    const uint64_t bytes = (uint64_t)words * 4;
+    const uint64_t bytes = (uint64_t)s_cw[CPG] * 4;
     if (threadIdx.x < 64) {
-        const uint64_t o = czk::lookback_wave(flags, c, bytes, status, nullptr);
+        const uint64_t o = czk::lookback_wave(flags, g, bytes, status, nullptr);
         if (threadIdx.x == 0)
             s_off = o;
     }
     __syncthreads();
     const uint64_t off = s_off;
-    if (threadIdx.x == 0) {
-        if (c == 0)
-            offs[0] = 0;
-        offs[c + 1] = off + bytes;
-        if (c + 1 == nchunks)
-            *total = off + bytes;
+    if (threadIdx.x <= (uint32_t)nc) {
+        const int j = threadIdx.x;
+        if (j > 0 || g == 0)
+            offs[c0 + j] = off + (uint64_t)s_cw[j] * 4;  // chunk c0 + j starts here (c0 + nc: the end)
     }
+    if (threadIdx.x == 0 && c0 + nc == nchunks)
+        *total = off + bytes;
     uint32_t *dst = reinterpret_cast<uint32_t *>(payload + off);
-    for (uint32_t w = threadIdx.x; w < words; w += ENC_THREADS)
-        dst[w] = s_words[w];
+    for (int j = 0; j < nc; ++j) {
+        const uint32_t w0 = s_cw[j], nw = s_cw[j + 1] - w0;
+        for (uint32_t w = threadIdx.x; w < nw; w += ENC_THREADS)
+            dst[w0 + w] = s_words[j][w];
+    }
 }
 
 // One thread a chunk; table[k] = symbol | length << 8 for the next 12 bits k.
-// A thread reads its chunk in groups of GW words, the next group in flight
-// while the current one is decoded (a word at a time into a 64-bit window),
-// so a refill rarely waits for memory.  Words past the chunk's end are read
-// (clamped to the payload) but never decoded from: a prefix code decides each
-// symbol by its own bits, and the bits a chunk's symbols use must lie within
-// its words.
+// A thread reads its chunk in groups of GB 16-byte blocks, the next group in
+// flight while the current one is decoded (a word at a time into a 64-bit
+// window, then as many symbols as the window holds).  Blocks may extend past
+// the chunk's words (into the next chunk, or zeros past the payload): a prefix
+// code decides each symbol by its own bits, and the bits the chunk's symbols
+// use must lie within its words.
 constexpr int DEC_THREADS = 64;  // small workgroups: a short stream has few chunks
-constexpr int GW = 16;
+constexpr int GB = 4;            // 16-byte blocks a group
 
 __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__restrict__ payload,
                                                              uint64_t payload_bytes,
@@ -218,26 +258,45 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
         atomicOr(status, czk::STATUS_FORMAT);  // symbols but no bits
         return;
     }
+    const uint32_t nbits = (uint32_t)min<uint64_t>((o1 - o0) * 8, 1u << 31);  // a chunk needs < 2^16
+    const uint4 *pb = reinterpret_cast<const uint4 *>(payload);  // 16-byte aligned
     const uint32_t *pw = reinterpret_cast<const uint32_t *>(payload);
-    const uint64_t last = payload_bytes / 4 - 1;  // payload_bytes >= o1 >= 4
-    const uint64_t w0 = o0 / 4;
-    const uint64_t nbits = (o1 - o0) * 8;
-    uint32_t cur[GW], nxt[GW];
+    const uint64_t nblk = payload_bytes / 16, nwords = payload_bytes / 4;
+    auto block = [&](uint64_t bi) -> uint4 {
+        if (bi < nblk)
+            return pb[bi];
+        uint4 v{0u, 0u, 0u, 0u};  // the payload's partial last block, zeros past its end
+        const uint64_t w = bi * 4;
+        if (w < nwords)
+            v.x = pw[w];
+        if (w + 1 < nwords)
+            v.y = pw[w + 1];
+        if (w + 2 < nwords)
+            v.z = pw[w + 2];
+        return v;
+    };
+    const uint64_t b0 = o0 / 16;       // block holding the chunk's first word
+    int skip = (int)((o0 / 4) % 4);    // words of that block before the chunk
+    uint4 cur[GB], nxt[GB];
 #pragma unroll
-    for (int k = 0; k < GW; ++k)
-        cur[k] = pw[min(w0 + k, last)];
+    for (int k = 0; k < GB; ++k)
+        cur[k] = block(b0 + k);
 #pragma unroll
-    for (int k = 0; k < GW; ++k)
-        nxt[k] = pw[min(w0 + GW + k, last)];
-    uint64_t window = 0, used = 0, g = 0;
-    uint32_t avail = 0, i = 0, pack = 0;
+    for (int k = 0; k < GB; ++k)
+        nxt[k] = block(b0 + GB + k);
+    uint64_t window = 0, g = 0;
+    uint32_t avail = 0, i = 0, pack = 0, used = 0;
     uint32_t *o32 = reinterpret_cast<uint32_t *>(out + start);
     while (i < n) {
 #pragma unroll
-        for (int k = 0; k < GW; ++k) {
+        for (int k = 0; k < 4 * GB; ++k) {
+            if (k < skip)
+                continue;
             if (i >= n)
                 break;
-            window |= (uint64_t)cur[k] << avail;  // avail < MAXLEN here
+            const uint4 v = cur[k / 4];
+            const uint32_t w = k % 4 == 0 ? v.x : k % 4 == 1 ? v.y : k % 4 == 2 ? v.z : v.w;
+            window |= (uint64_t)w << avail;  // avail < MAXLEN here
             avail += 32;
             while (avail >= (uint32_t)MAXLEN && i < n) {
                 const uint16_t e = s_tab[window & ((1u << MAXLEN) - 1)];
@@ -257,14 +316,15 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
                 ++i;
             }
         }
+        skip = 0;
         // the next group becomes current; the one after it is requested
         ++g;
 #pragma unroll
-        for (int k = 0; k < GW; ++k)
+        for (int k = 0; k < GB; ++k)
             cur[k] = nxt[k];
 #pragma unroll
-        for (int k = 0; k < GW; ++k)
-            nxt[k] = pw[min(w0 + (g + 1) * GW + k, last)];
+        for (int k = 0; k < GB; ++k)
+            nxt[k] = block(b0 + (g + 1) * GB + k);
     }
     if (n % 4)
         for (uint32_t k = 0; k < n % 4; ++k)
@@ -381,9 +441,10 @@ int cz_huff_encode(cz_ctx *ctx, const void *d_in, size_t nbytes, void *d_out, si
     const uint8_t *in = static_cast<const uint8_t *>(d_in);
     uint8_t *out = static_cast<uint8_t *>(d_out);
     // workspace: histogram (256 u64), code table (256 u32), ticket, status,
-    // payload size, then the look-back flags (one u64 a chunk)
+    // payload size, then the look-back flags (one u64 a group of chunks)
     constexpr size_t W_HIST = 0, W_CODE = 2048, W_TICKET = 3072, W_STATUS = 3076, W_TOTAL = 3080, W_FLAGS = 3088;
-    int rc = ctx->huff.ensure(W_FLAGS + nchunks * 8);
+    const uint64_t ngroups = (nchunks + CPG - 1) / CPG;
+    int rc = ctx->huff.ensure(W_FLAGS + ngroups * 8);
     if (rc != CZ_OK)
         return rc;
     uint8_t *w = static_cast<uint8_t *>(ctx->huff.ptr);
@@ -423,11 +484,11 @@ int cz_huff_encode(cz_ctx *ctx, const void *d_in, size_t nbytes, void *d_out, si
     if (hipMemcpyAsync(out, staged, HEAD, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(code, staged + HEAD, 1024, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemsetAsync(out + HEAD + 8 * (nchunks + 1), 0, p0 - (HEAD + 8 * (nchunks + 1)), st) != hipSuccess ||
-        hipMemsetAsync(w + W_TICKET, 0, W_FLAGS - W_TICKET + nchunks * 8, st) != hipSuccess)
+        hipMemsetAsync(w + W_TICKET, 0, W_FLAGS - W_TICKET + ngroups * 8, st) != hipSuccess)
         return CZ_ERR_HIP;
     uint64_t *offs = reinterpret_cast<uint64_t *>(out + HEAD);
     if (nchunks) {
-        hipLaunchKernelGGL(encode_kernel, dim3((unsigned)nchunks), dim3(ENC_THREADS), 0, st, in, (uint64_t)nbytes,
+        hipLaunchKernelGGL(encode_kernel, dim3((unsigned)ngroups), dim3(ENC_THREADS), 0, st, in, (uint64_t)nbytes,
                            code, nchunks, reinterpret_cast<uint64_t *>(w + W_FLAGS),
                            reinterpret_cast<uint32_t *>(w + W_TICKET), offs, out + p0, total,
                            reinterpret_cast<uint32_t *>(w + W_STATUS));
@@ -448,7 +509,7 @@ int cz_huff_encode(cz_ctx *ctx, const void *d_in, size_t nbytes, void *d_out, si
 
 int cz_huff_decode(cz_ctx *ctx, const void *d_in, size_t in_bytes, void *d_out, size_t out_cap, void *stream)
 {
-    if (!ctx || !d_in || in_bytes < HEAD || reinterpret_cast<uintptr_t>(d_in) % 8)
+    if (!ctx || !d_in || in_bytes < HEAD || reinterpret_cast<uintptr_t>(d_in) % 16)
         return CZ_ERR_ARG;
     czh::DeviceGuard guard(ctx->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -500,11 +561,13 @@ int cz_huff_decode(cz_ctx *ctx, const void *d_in, size_t in_bytes, void *d_out, 
     if (rc != CZ_OK)
         return rc;
     const uint8_t *in = static_cast<const uint8_t *>(d_in);
-    const unsigned g = (unsigned)((nchunks + DEC_THREADS - 1) / DEC_THREADS);
-    hipLaunchKernelGGL(decode_kernel, dim3(g), dim3(DEC_THREADS), 0, st, in + p0, (uint64_t)(in_bytes - p0),
-                       reinterpret_cast<const uint64_t *>(in + HEAD),
-                       static_cast<const uint16_t *>(ctx->huff_stage.dev.ptr), nchunks, raw,
-                       static_cast<uint8_t *>(d_out), &ctx->work->status);
+    const uint8_t *payload = in + p0;
+    const uint64_t pbytes = in_bytes - p0;
+    const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + HEAD);
+    const uint16_t *tab = static_cast<const uint16_t *>(ctx->huff_stage.dev.ptr);
+    uint8_t *dst = static_cast<uint8_t *>(d_out);
+    hipLaunchKernelGGL(decode_kernel, dim3((unsigned)((nchunks + DEC_THREADS - 1) / DEC_THREADS)),
+                       dim3(DEC_THREADS), 0, st, payload, pbytes, offs, tab, nchunks, raw, dst, &ctx->work->status);
     return hipGetLastError() == hipSuccess ? CZ_OK : CZ_ERR_HIP;
 }
 

@@ -145,6 +145,12 @@ def test_huffman_errors(codec):
     with pytest.raises(_cz.CzError) as e:
         decode(blob, raw=host.size - 1)  # output too small for the raw size
     assert e.value.code == _cz.ERR_CAPACITY
+    shifted = torch.zeros(len(blob) + 16, dtype=torch.uint8, device="cuda")
+    shifted[8:8 + len(blob)] = torch.frombuffer(bytearray(blob), dtype=torch.uint8).cuda()
+    outb = torch.empty(host.size, dtype=torch.uint8, device="cuda")
+    with pytest.raises(_cz.CzError) as e:  # the container must start 16-byte aligned
+        codec.ctx.huff_decode(shifted.data_ptr() + 8, len(blob), outb.data_ptr(), outb.numel())
+    assert e.value.code == _cz.ERR_ARG
     # a payload bit pattern the single 1-bit code does not define
     bad = bytearray(blob)
     nchunks = (host.size + CHUNK - 1) // CHUNK
