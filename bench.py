@@ -503,12 +503,47 @@ def main_c5(args):
     print(json.dumps(line), flush=True)
 
 
+def main_lossless(args):
+    """The GPU lossless stage alone, on the streams of two of C3's fields:
+    rho (noisy: the stream is mostly kept coefficients) and u (smooth: mostly
+    masks and runs of zero bytes).  One JSON line: stream bytes through
+    encode + decode per second, with the per-field detail of gpu_lossless."""
+    import torch
+
+    from paper_1903_07761_amd import fields as G
+    from paper_1903_07761_amd.codec import Codec
+
+    dev = torch.device("cuda", 0)
+    codec = Codec(0)
+    log("generating rho and u (1024^3 float64)")
+    fields = [("rho", G.bubble_cloud(1024, 1905, v_in=0.016, dtype=torch.float64, device=dev)),
+              ("u", G.div_free_velocity(1024, 1907, dtype=torch.float64, device=dev)[0])]
+    streams, sizes, raw = [], [], []
+    for lab, t in fields:
+        buf, n = codec.compress(t, 32, "W3_ai", 1e-4 * G.value_range(t))
+        streams.append(buf)
+        sizes.append(n)
+        raw.append(t.numel() * t.element_size())
+    del fields
+    torch.cuda.empty_cache()
+    gl = gpu_lossless(codec, torch, streams, sizes, raw, [8, 8], reps=max(args.steps, 1))
+    t_enc = sum(n / (r * 1e9) for n, r in zip(sizes, gl["huff_encode_GBps"]))
+    t_dec = sum(n / (r * 1e9) for n, r in zip(sizes, gl["huff_decode_GBps"]))
+    line = {"metric": "GB/s of stream through the GPU lossless stage (encode + decode)",
+            "value": round(sum(sizes) / (t_enc + t_dec) / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 0, "higher_is_better": True, "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "byte shuffle + canonical Huffman (4 KiB chunks) of the W3_ai streams of two "
+                                   "1024^3 float64 fields of C3 (rho, u)", "stream_bytes": sizes},
+            "lossless_gpu": gl}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4", "c5", "lossless"])
     ap.add_argument("--requests", type=int, default=2000, help="c5: number of serving requests")
     ap.add_argument("--cpu-blocks", type=int, default=400, help="oracle sample: blocks per field")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -523,6 +558,8 @@ def main():
         return main_c4(args)
     if args.workload == "c5":
         return main_c5(args)
+    if args.workload == "lossless":
+        return main_lossless(args)
 
     import torch
 
