@@ -4,9 +4,9 @@
 //     position j * n + i (n whole elements), the tail bytes stay at the end;
 //   * Z-zeroing: clear the low bits of every stored detail coefficient
 //     (values outside the 4^3 coarse corner), after decimation.
-// Both are bandwidth-bound passes over the stream: one thread per element
-// for the shuffle (k-byte loads, byte stores that coalesce into 64-byte runs
-// per plane), one workgroup per record for the zeroing.
+// Both are bandwidth-bound passes over the stream: one thread per four
+// elements for the shuffle (16-byte loads, one 4-byte word into every plane),
+// one workgroup per record for the zeroing.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -28,30 +28,124 @@ struct Word<8> {
     using type = uint64_t;
 };
 
-template <int K>
-__global__ __launch_bounds__(THREADS) void shuffle_kernel(const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
-                                                          uint64_t n)
+// Byte j of element i, for four consecutive elements, as one 32-bit word
+// (element i in the low byte): the four bytes they put into plane j.
+template <int K, typename W>
+__device__ __forceinline__ uint32_t plane_word(const W (&e)[4], int j)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * THREADS + threadIdx.x; i < n; i += (uint64_t)gridDim.x * THREADS) {
-        using W = typename Word<K>::type;
-        const W w = *reinterpret_cast<const W *>(in + i * K);  // the element, one aligned load
+    return (uint32_t)((e[0] >> (8 * j)) & 0xFF) | (uint32_t)((e[1] >> (8 * j)) & 0xFF) << 8 |
+           (uint32_t)((e[2] >> (8 * j)) & 0xFF) << 16 | (uint32_t)((e[3] >> (8 * j)) & 0xFF) << 24;
+}
+
+// Store the 4 bytes of v at p with the widest stores p's alignment allows
+// (align = p's address mod 4, the same for every thread writing one plane,
+// since the planes start at out + j n and threads step by 4 bytes).
+__device__ __forceinline__ void store4(uint8_t *p, uint32_t v, uint32_t align)
+{
+    if (align % 4 == 0) {
+        *reinterpret_cast<uint32_t *>(p) = v;
+    } else if (align % 2 == 0) {
+        reinterpret_cast<uint16_t *>(p)[0] = (uint16_t)v;
+        reinterpret_cast<uint16_t *>(p)[1] = (uint16_t)(v >> 16);
+    } else {
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            out[(uint64_t)j * n + i] = (uint8_t)(w >> (8 * j));
+        for (int k = 0; k < 4; ++k)
+            p[k] = (uint8_t)(v >> (8 * k));
     }
 }
 
-template <int K>
-__global__ __launch_bounds__(THREADS) void unshuffle_kernel(const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
-                                                            uint64_t n)
+__device__ __forceinline__ uint32_t load4(const uint8_t *p, uint32_t align)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * THREADS + threadIdx.x; i < n; i += (uint64_t)gridDim.x * THREADS) {
-        using W = typename Word<K>::type;
-        W w = 0;
+    if (align % 4 == 0)
+        return *reinterpret_cast<const uint32_t *>(p);
+    if (align % 2 == 0)
+        return (uint32_t)reinterpret_cast<const uint16_t *>(p)[0] |
+               (uint32_t)reinterpret_cast<const uint16_t *>(p)[1] << 16;
+    return (uint32_t)p[0] | (uint32_t)p[1] << 8 | (uint32_t)p[2] << 16 | (uint32_t)p[3] << 24;
+}
+
+// One thread per four consecutive elements: their 4 K bytes are read in one
+// or two 16-byte loads (element loads when the input is not 16-byte aligned),
+// and each plane receives one 4-byte word, so a wavefront writes 256
+// consecutive bytes of every plane.  The last n % 4 elements go byte by byte.
+template <int K>
+__global__ __launch_bounds__(THREADS) void shuffle_kernel(const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
+                                                          uint64_t n, int wide)
+{
+    using W = typename Word<K>::type;
+    const uint64_t groups = n / 4;
+    for (uint64_t g = (uint64_t)blockIdx.x * THREADS + threadIdx.x; g < groups; g += (uint64_t)gridDim.x * THREADS) {
+        const uint64_t i = 4 * g;
+        W e[4];
+        if (wide) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(in + i * K);
+            if constexpr (K == 4) {
+                const uint4 v = src[0];
+                e[0] = v.x;
+                e[1] = v.y;
+                e[2] = v.z;
+                e[3] = v.w;
+            } else {
+                const uint4 v0 = src[0], v1 = src[1];
+                e[0] = (W)v0.x | (W)v0.y << 32;
+                e[1] = (W)v0.z | (W)v0.w << 32;
+                e[2] = (W)v1.x | (W)v1.y << 32;
+                e[3] = (W)v1.z | (W)v1.w << 32;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                e[k] = reinterpret_cast<const W *>(in + i * K)[k];
+        }
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            w |= (W)in[(uint64_t)j * n + i] << (8 * j);
-        *reinterpret_cast<W *>(out + i * K) = w;  // the element, one aligned store
+            store4(out + (uint64_t)j * n + i, plane_word<K>(e, j),
+                   (uint32_t)((reinterpret_cast<uintptr_t>(out) + (uint64_t)j * n) % 4));
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (n % 4) * K) {
+        const uint64_t i = 4 * groups + threadIdx.x / K;
+        const int j = (int)(threadIdx.x % K);
+        out[(uint64_t)j * n + i] = in[i * K + j];
+    }
+}
+
+// The inverse: each thread gathers one 4-byte word from every plane and
+// writes its four elements with one or two 16-byte stores.
+template <int K>
+__global__ __launch_bounds__(THREADS) void unshuffle_kernel(const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
+                                                            uint64_t n, int wide)
+{
+    using W = typename Word<K>::type;
+    const uint64_t groups = n / 4;
+    for (uint64_t g = (uint64_t)blockIdx.x * THREADS + threadIdx.x; g < groups; g += (uint64_t)gridDim.x * THREADS) {
+        const uint64_t i = 4 * g;
+        W e[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t v =
+                load4(in + (uint64_t)j * n + i, (uint32_t)((reinterpret_cast<uintptr_t>(in) + (uint64_t)j * n) % 4));
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                e[k] |= (W)((v >> (8 * k)) & 0xFF) << (8 * j);
+        }
+        if (wide) {
+            uint4 *dst = reinterpret_cast<uint4 *>(out + i * K);
+            if constexpr (K == 4) {
+                dst[0] = uint4{e[0], e[1], e[2], e[3]};
+            } else {
+                dst[0] = uint4{(uint32_t)e[0], (uint32_t)(e[0] >> 32), (uint32_t)e[1], (uint32_t)(e[1] >> 32)};
+                dst[1] = uint4{(uint32_t)e[2], (uint32_t)(e[2] >> 32), (uint32_t)e[3], (uint32_t)(e[3] >> 32)};
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                reinterpret_cast<W *>(out + i * K)[k] = e[k];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (n % 4) * K) {
+        const uint64_t i = 4 * groups + threadIdx.x / K;
+        const int j = (int)(threadIdx.x % K);
+        out[i * K + j] = in[(uint64_t)j * n + i];
     }
 }
 
@@ -110,9 +204,11 @@ __global__ __launch_bounds__(THREADS) void zero_kernel(uint8_t *stream, uint64_t
     }
 }
 
+// Workgroups for n elements handled four at a time (at least one, for the
+// last n % 4 elements).
 int grid_for(uint64_t n)
 {
-    uint64_t g = (n + THREADS - 1) / THREADS;
+    uint64_t g = (n / 4 + THREADS - 1) / THREADS;
     return (int)(g > 65536 ? 65536 : g < 1 ? 1 : g);
 }
 
@@ -132,11 +228,12 @@ int cz_shuffle(const void *d_in, size_t nbytes, uint32_t elem, void *d_out, void
     const uint64_t n = nbytes / elem;
     const uint8_t *in = static_cast<const uint8_t *>(d_in);
     uint8_t *out = static_cast<uint8_t *>(d_out);
+    const int wide = reinterpret_cast<uintptr_t>(in) % 16 == 0;
     if (n) {
         if (elem == 4)
-            hipLaunchKernelGGL(shuffle_kernel<4>, dim3(grid_for(n)), dim3(THREADS), 0, st, in, out, n);
+            hipLaunchKernelGGL(shuffle_kernel<4>, dim3(grid_for(n)), dim3(THREADS), 0, st, in, out, n, wide);
         else
-            hipLaunchKernelGGL(shuffle_kernel<8>, dim3(grid_for(n)), dim3(THREADS), 0, st, in, out, n);
+            hipLaunchKernelGGL(shuffle_kernel<8>, dim3(grid_for(n)), dim3(THREADS), 0, st, in, out, n, wide);
         if (hipGetLastError() != hipSuccess)
             return CZ_ERR_HIP;
     }
@@ -158,11 +255,12 @@ int cz_unshuffle(const void *d_in, size_t nbytes, uint32_t elem, void *d_out, vo
     const uint64_t n = nbytes / elem;
     const uint8_t *in = static_cast<const uint8_t *>(d_in);
     uint8_t *out = static_cast<uint8_t *>(d_out);
+    const int wide = reinterpret_cast<uintptr_t>(out) % 16 == 0;
     if (n) {
         if (elem == 4)
-            hipLaunchKernelGGL(unshuffle_kernel<4>, dim3(grid_for(n)), dim3(THREADS), 0, st, in, out, n);
+            hipLaunchKernelGGL(unshuffle_kernel<4>, dim3(grid_for(n)), dim3(THREADS), 0, st, in, out, n, wide);
         else
-            hipLaunchKernelGGL(unshuffle_kernel<8>, dim3(grid_for(n)), dim3(THREADS), 0, st, in, out, n);
+            hipLaunchKernelGGL(unshuffle_kernel<8>, dim3(grid_for(n)), dim3(THREADS), 0, st, in, out, n, wide);
         if (hipGetLastError() != hipSuccess)
             return CZ_ERR_HIP;
     }

@@ -34,6 +34,36 @@ def test_shuffle_matches_oracle(codec, elem):
     say(f"[shuffle] elem {elem} ok")
 
 
+@pytest.mark.parametrize("elem", [4, 8])
+def test_shuffle_alignments(codec, elem):
+    """Element counts of every residue mod 4 (planes starting at every
+    alignment), inputs that are element- but not 16-byte-aligned, and outputs
+    at odd addresses: the word-wide plane accesses fall back to narrower ones
+    and the results stay byte-identical to the oracle's."""
+    from oracle import precond
+    from paper_1903_07761_amd import _cz
+
+    rng = np.random.default_rng(100 + elem)
+    for nel in (4097, 4098, 4099, 4100, 65541):
+        nbytes = nel * elem + 3  # three tail bytes as well
+        host = rng.integers(0, 256, nbytes, dtype=np.uint8)
+        ref = precond.shuffle(host.tobytes(), elem)
+        for in_off, out_off in ((0, 0), (elem, 1), (elem, 2), (0, 3)):
+            src = torch.zeros(nbytes + 32, dtype=torch.uint8, device="cuda")
+            src[in_off:in_off + nbytes] = torch.from_numpy(host).cuda()
+            dst = torch.zeros(nbytes + 32, dtype=torch.uint8, device="cuda")
+            _cz.shuffle(src.data_ptr() + in_off, nbytes, elem, dst.data_ptr() + out_off)
+            torch.cuda.synchronize()
+            got = dst[out_off:out_off + nbytes].cpu().numpy().tobytes()
+            assert got == ref, (nel, in_off, out_off)
+            # unshuffle from a plane buffer at an odd offset into an element-aligned output
+            back = torch.zeros(nbytes + 32, dtype=torch.uint8, device="cuda")
+            _cz.unshuffle(dst.data_ptr() + out_off, nbytes, elem, back.data_ptr() + in_off)
+            torch.cuda.synchronize()
+            assert back[in_off:in_off + nbytes].cpu().numpy().tobytes() == host.tobytes(), (nel, in_off, out_off)
+    say(f"[shuffle] elem {elem} alignments ok")
+
+
 def test_shuffle_rejects_bad_arguments(codec):
     from paper_1903_07761_amd import _cz
 
