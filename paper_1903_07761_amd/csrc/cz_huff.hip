@@ -20,7 +20,7 @@
 // packed with LDS atomics, the group placed by a decoupled look-back over the
 // group sizes and copied out whole): two reads of the input.  Decoding: one thread
 // a chunk with a 4096-entry lookup table in LDS, the chunk's words read
-// ahead in 16-byte blocks.
+// ahead in 16-byte blocks (two loop shapes, by the stream's mean code length).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -225,15 +225,23 @@ __global__ __launch_bounds__(ENC_THREADS) void encode_kernel(const uint8_t *__re
 }
 
 // One thread a chunk; table[k] = symbol | length << 8 for the next 12 bits k.
-// A thread reads its chunk in groups of GB 16-byte blocks, the next group in
-// flight while the current one is decoded (a word at a time into a 64-bit
-// window, then as many symbols as the window holds).  Blocks may extend past
-// the chunk's words (into the next chunk, or zeros past the payload): a prefix
-// code decides each symbol by its own bits, and the bits the chunk's symbols
-// use must lie within its words.
+// The chunk's words come from 16-byte blocks of the payload, read ahead.
+// Blocks may extend past the chunk's words (into the next chunk, or zeros
+// past the payload): a prefix code decides each symbol by its own bits, and
+// the bits the chunk's symbols use must lie within its words.  Two loop
+// shapes, chosen per stream by its mean code length:
+//   * GROUPED (mean >= 4 bits): groups of GB blocks, the next group in
+//     flight; each word enters a 64-bit window and the window is emptied
+//     symbol by symbol.  With long codes every lane takes about as many
+//     symbols per word, so the lanes stay together.
+//   * FLAT (short codes, skewed streams): every iteration decodes one symbol
+//     on every lane, refilling a lane's window from the next word when it
+//     holds fewer than 12 bits; a lane whose words are mostly 1-bit codes no
+//     longer holds back the others word by word.
 constexpr int DEC_THREADS = 64;  // small workgroups: a short stream has few chunks
 constexpr int GB = 4;            // 16-byte blocks a group
 
+template <bool FLAT>
 __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__restrict__ payload,
                                                              uint64_t payload_bytes,
                                                              const uint64_t *__restrict__ offs,
@@ -275,56 +283,86 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
             v.z = pw[w + 2];
         return v;
     };
-    const uint64_t b0 = o0 / 16;       // block holding the chunk's first word
-    int skip = (int)((o0 / 4) % 4);    // words of that block before the chunk
-    uint4 cur[GB], nxt[GB];
-#pragma unroll
-    for (int k = 0; k < GB; ++k)
-        cur[k] = block(b0 + k);
-#pragma unroll
-    for (int k = 0; k < GB; ++k)
-        nxt[k] = block(b0 + GB + k);
-    uint64_t window = 0, g = 0;
-    uint32_t avail = 0, i = 0, pack = 0, used = 0;
+    uint64_t window = 0;
+    uint32_t avail = 0, used = 0, pack = 0, i = 0;
     uint32_t *o32 = reinterpret_cast<uint32_t *>(out + start);
-    while (i < n) {
-#pragma unroll
-        for (int k = 0; k < 4 * GB; ++k) {
-            if (k < skip)
-                continue;
-            if (i >= n)
-                break;
-            const uint4 v = cur[k / 4];
-            const uint32_t w = k % 4 == 0 ? v.x : k % 4 == 1 ? v.y : k % 4 == 2 ? v.z : v.w;
-            window |= (uint64_t)w << avail;  // avail < MAXLEN here
-            avail += 32;
-            while (avail >= (uint32_t)MAXLEN && i < n) {
-                const uint16_t e = s_tab[window & ((1u << MAXLEN) - 1)];
-                const uint32_t l = e >> 8;
-                used += l;
-                if (l == 0 || used > nbits) {  // no such code, or past the chunk's bits
-                    atomicOr(status, czk::STATUS_FORMAT);
-                    return;
+    // decode one symbol from the window (at least MAXLEN bits in it); false on a bad code
+    auto one = [&]() -> bool {
+        const uint16_t e = s_tab[window & ((1u << MAXLEN) - 1)];
+        const uint32_t l = e >> 8;
+        used += l;
+        if (l == 0 || used > nbits)  // no such code, or past the chunk's bits
+            return false;
+        window >>= l;
+        avail -= l;
+        pack |= (uint32_t)(e & 0xFF) << (8 * (i % 4));
+        if (i % 4 == 3) {
+            o32[i / 4] = pack;
+            pack = 0;
+        }
+        ++i;
+        return true;
+    };
+    if constexpr (FLAT) {
+        uint64_t bi = o0 / 16;
+        uint32_t wi = (uint32_t)(o0 / 4) % 4;  // next word of cur
+        uint4 cur = block(bi), n1 = block(bi + 1), n2 = block(bi + 2);
+        while (i < n) {
+            if (avail < (uint32_t)MAXLEN) {
+                const uint32_t w = wi == 0 ? cur.x : wi == 1 ? cur.y : wi == 2 ? cur.z : cur.w;
+                window |= (uint64_t)w << avail;
+                avail += 32;
+                if (++wi == 4) {
+                    wi = 0;
+                    cur = n1;
+                    n1 = n2;
+                    n2 = block(++bi + 2);
                 }
-                window >>= l;
-                avail -= l;
-                pack |= (uint32_t)(e & 0xFF) << (8 * (i % 4));
-                if (i % 4 == 3) {
-                    o32[i / 4] = pack;
-                    pack = 0;
-                }
-                ++i;
+            }
+            if (!one()) {
+                atomicOr(status, czk::STATUS_FORMAT);
+                return;
             }
         }
-        skip = 0;
-        // the next group becomes current; the one after it is requested
-        ++g;
+    } else {
+        const uint64_t b0 = o0 / 16;     // block holding the chunk's first word
+        int skip = (int)((o0 / 4) % 4);  // words of that block before the chunk
+        uint4 cur[GB], nxt[GB];
 #pragma unroll
         for (int k = 0; k < GB; ++k)
-            cur[k] = nxt[k];
+            cur[k] = block(b0 + k);
 #pragma unroll
         for (int k = 0; k < GB; ++k)
-            nxt[k] = block(b0 + (g + 1) * GB + k);
+            nxt[k] = block(b0 + GB + k);
+        uint64_t g = 0;
+        while (i < n) {
+#pragma unroll
+            for (int k = 0; k < 4 * GB; ++k) {
+                if (k < skip)
+                    continue;
+                if (i >= n)
+                    break;
+                const uint4 v = cur[k / 4];
+                const uint32_t w = k % 4 == 0 ? v.x : k % 4 == 1 ? v.y : k % 4 == 2 ? v.z : v.w;
+                window |= (uint64_t)w << avail;  // avail < MAXLEN here
+                avail += 32;
+                while (avail >= (uint32_t)MAXLEN && i < n) {
+                    if (!one()) {
+                        atomicOr(status, czk::STATUS_FORMAT);
+                        return;
+                    }
+                }
+            }
+            skip = 0;
+            // the next group becomes current; the one after it is requested
+            ++g;
+#pragma unroll
+            for (int k = 0; k < GB; ++k)
+                cur[k] = nxt[k];
+#pragma unroll
+            for (int k = 0; k < GB; ++k)
+                nxt[k] = block(b0 + (g + 1) * GB + k);
+        }
     }
     if (n % 4)
         for (uint32_t k = 0; k < n % 4; ++k)
@@ -566,8 +604,14 @@ int cz_huff_decode(cz_ctx *ctx, const void *d_in, size_t in_bytes, void *d_out, 
     const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + HEAD);
     const uint16_t *tab = static_cast<const uint16_t *>(ctx->huff_stage.dev.ptr);
     uint8_t *dst = static_cast<uint8_t *>(d_out);
-    hipLaunchKernelGGL(decode_kernel, dim3((unsigned)((nchunks + DEC_THREADS - 1) / DEC_THREADS)),
-                       dim3(DEC_THREADS), 0, st, payload, pbytes, offs, tab, nchunks, raw, dst, &ctx->work->status);
+    // mean code length from the payload size: short codes take the flat loop
+    const dim3 grid((unsigned)((nchunks + DEC_THREADS - 1) / DEC_THREADS)), threads(DEC_THREADS);
+    if (pbytes * 8 < 4 * raw)
+        hipLaunchKernelGGL(decode_kernel<true>, grid, threads, 0, st, payload, pbytes, offs, tab, nchunks, raw, dst,
+                           &ctx->work->status);
+    else
+        hipLaunchKernelGGL(decode_kernel<false>, grid, threads, 0, st, payload, pbytes, offs, tab, nchunks, raw, dst,
+                           &ctx->work->status);
     return hipGetLastError() == hipSuccess ? CZ_OK : CZ_ERR_HIP;
 }
 

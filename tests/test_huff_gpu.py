@@ -46,6 +46,9 @@ def shuffled_stream(codec, seed):
 
 
 def inputs(codec):
+    """Short codes (under 4 bits a byte: one symbol, two symbols, geometric,
+    Fibonacci) take the decoder's one-symbol-a-step loop; the others its
+    word-group loop."""
     rng = np.random.default_rng(5)
     yield "empty", np.zeros(0, np.uint8)
     yield "one byte", np.array([200], np.uint8)
@@ -164,6 +167,13 @@ def test_huffman_errors(codec):
     torch.cuda.synchronize()
     assert codec.status() == _cz.ERR_FORMAT
     assert codec.status() == 0
+    # the same for long codes (8 bits a byte: the word-group decoder)
+    wide = np.random.default_rng(3).integers(0, 256, 3 * CHUNK + 5, dtype=np.uint8)
+    wblob = huffman.encode(wide.tobytes())
+    d = torch.frombuffer(bytearray(wblob), dtype=torch.uint8).cuda()
+    codec.huff_decode(d, len(wblob) - 8, wide.size)
+    torch.cuda.synchronize()
+    assert codec.status() == _cz.ERR_FORMAT
     # a valid container still decodes after the errors
     out = decode(blob)
     torch.cuda.synchronize()
