@@ -396,7 +396,7 @@ void package_merge(const uint64_t counts[256], uint8_t lengths[256])
         leaves[i].mult[i] = 1;
     }
     std::vector<Item> cur = leaves;
-    for (int round = 0; round < MAXLEN - 1; ++round) {
+    for (int step = 0; step < MAXLEN - 1; ++step) {
         std::vector<Item> packages;
         for (size_t i = 0; i + 1 < cur.size(); i += 2) {
             Item p;
