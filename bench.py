@@ -554,6 +554,11 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
     if args.workload == "c4":
         return main_c4(args)
     if args.workload == "c5":
@@ -561,14 +566,9 @@ def main():
     if args.workload == "lossless":
         return main_lossless(args)
 
-    import torch
-
     from paper_1903_07761_amd import metrics
     from paper_1903_07761_amd.codec import Codec
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a HIP device", file=sys.stderr)
-        sys.exit(2)
     dev = torch.device("cuda", 0)
     codec = Codec(0)
     items, desc = workload(args.workload, dev)
