@@ -78,3 +78,19 @@ def test_read_header_parses_oracle_stream(czlib, oracle):
 def test_strerror(czlib):
     assert czlib.strerror(0) == "ok"
     assert "stream" in czlib.strerror(czlib.ERR_FORMAT)
+
+
+def test_huff_bound_matches_container_layout(czlib):
+    """Worst case of the lossless container: 32-byte header, 256 lengths,
+    (chunks + 1) offsets padded to 16, and 12 bits a byte for every 4 KiB
+    chunk (1536 words); the oracle's container of any input fits."""
+    from oracle import huffman
+
+    for n in (0, 1, 4095, 4096, 4097, 10 * 4096 + 3):
+        chunks = (n + 4095) // 4096
+        head = (288 + 8 * (chunks + 1) + 15) // 16 * 16
+        assert czlib.huff_bound(n) == head + chunks * 1536 * 4, n
+    import numpy as np
+
+    data = np.random.default_rng(1).integers(0, 256, 3 * 4096 + 11, dtype=np.uint8).tobytes()
+    assert len(huffman.encode(data)) <= czlib.huff_bound(len(data))
