@@ -385,41 +385,48 @@ void package_merge(const uint64_t counts[256], uint8_t lengths[256])
     }
     const int n = (int)used.size();
     std::stable_sort(used.begin(), used.end(), [&](int a, int b) { return counts[a] < counts[b]; });
+    // list[l]: the leaves merged with the packages of list[l - 1] (package j
+    // pairs its items 2 j and 2 j + 1).  An item is a leaf position (>= 0) or
+    // -1 - j for package j.
     struct Item {
         uint64_t w;
-        std::vector<uint16_t> mult;  // per leaf position
+        int what;
     };
-    std::vector<Item> leaves(n);
-    for (int i = 0; i < n; ++i) {
-        leaves[i].w = counts[used[i]];
-        leaves[i].mult.assign(n, 0);
-        leaves[i].mult[i] = 1;
-    }
-    std::vector<Item> cur = leaves;
-    for (int step = 0; step < MAXLEN - 1; ++step) {
-        std::vector<Item> packages;
-        for (size_t i = 0; i + 1 < cur.size(); i += 2) {
-            Item p;
-            p.w = cur[i].w + cur[i + 1].w;
-            p.mult = cur[i].mult;
-            for (int k = 0; k < n; ++k)
-                p.mult[k] += cur[i + 1].mult[k];
-            packages.push_back(std::move(p));
+    std::vector<std::vector<Item>> list(MAXLEN);
+    for (int i = 0; i < n; ++i)
+        list[0].push_back({counts[used[i]], i});
+    for (int l = 1; l < MAXLEN; ++l) {
+        const std::vector<Item> &prev = list[l - 1];
+        std::vector<Item> &cur = list[l];
+        const int np = (int)prev.size() / 2;
+        int i = 0, j = 0;
+        while (i < n || j < np) {
+            const uint64_t pw = j < np ? prev[2 * j].w + prev[2 * j + 1].w : 0;
+            if (j >= np || (i < n && list[0][i].w <= pw)) {
+                cur.push_back(list[0][i]);
+                ++i;
+            } else {
+                cur.push_back({pw, -1 - j});
+                ++j;
+            }
         }
-        std::vector<Item> out;
-        size_t i = 0, j = 0;
-        while (i < leaves.size() || j < packages.size()) {
-            if (j >= packages.size() || (i < leaves.size() && leaves[i].w <= packages[j].w))
-                out.push_back(leaves[i++]);
-            else
-                out.push_back(std::move(packages[j++]));
-        }
-        cur = std::move(out);
     }
+    // The first 2 n - 2 items of the last list are chosen; the packages in a
+    // chosen prefix are packages 0 .. p - 1, which choose the first 2 p items
+    // of the list below.  A leaf's length is the number of lists in whose
+    // chosen prefix it appears.
     std::vector<int> len(n, 0);
-    for (int i = 0; i < 2 * n - 2; ++i)
-        for (int k = 0; k < n; ++k)
-            len[k] += cur[i].mult[k];
+    int sel = 2 * n - 2;
+    for (int l = MAXLEN - 1; l >= 0; --l) {
+        int p = 0;
+        for (int k = 0; k < sel; ++k) {
+            if (list[l][k].what >= 0)
+                ++len[list[l][k].what];
+            else
+                ++p;
+        }
+        sel = 2 * p;
+    }
     for (int k = 0; k < n; ++k)
         lengths[used[k]] = (uint8_t)len[k];
 }
