@@ -19,8 +19,9 @@
 // counts, and one encoding kernel (one workgroup a group of chunks, codes
 // packed with LDS atomics, the group placed by a decoupled look-back over the
 // group sizes and copied out whole): two reads of the input.  Decoding: one thread
-// a chunk with a 4096-entry lookup table in LDS, the chunk's words read
-// ahead in 16-byte blocks (two loop shapes, by the stream's mean code length).
+// a chunk with a 4096-entry lookup table in LDS, the lanes of a wavefront in
+// lockstep, the chunk's words read ahead into an LDS ring and the decoded
+// words staged in LDS and written by the whole wavefront.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -224,24 +225,53 @@ __global__ __launch_bounds__(ENC_THREADS) void encode_kernel(const uint8_t *__re
     }
 }
 
-// One thread a chunk; table[k] = symbol | length << 8 for the next 12 bits k.
-// The chunk's words come from 16-byte blocks of the payload, read ahead.
-// Blocks may extend past the chunk's words (into the next chunk, or zeros
-// past the payload): a prefix code decides each symbol by its own bits, and
-// the bits the chunk's symbols use must lie within its words.  Two loop
-// shapes, chosen per stream by its mean code length:
-//   * GROUPED (mean >= 4 bits): groups of GB blocks, the next group in
-//     flight; each word enters a 64-bit window and the window is emptied
-//     symbol by symbol.  With long codes every lane takes about as many
-//     symbols per word, so the lanes stay together.
-//   * FLAT (short codes, skewed streams): every iteration decodes one symbol
-//     on every lane, refilling a lane's window from the next word when it
-//     holds fewer than 12 bits; a lane whose words are mostly 1-bit codes no
-//     longer holds back the others word by word.
-constexpr int DEC_THREADS = 64;  // small workgroups: a short stream has few chunks
-constexpr int GB = 4;            // 16-byte blocks a group
+constexpr int DEC_THREADS = 64;  // one wavefront: a short stream has few chunks, and the
+                                 // lanes' lockstep below is the wavefront's
+static_assert(DEC_THREADS == 64, "the decoder's workgroup is one wavefront");
 
-template <bool FLAT>
+// Decoding: one thread a chunk, table[k] = symbol | length << 8 for the next
+// 12 bits k (in LDS), one symbol a step on every lane, and every vector
+// memory access issued by all lanes at fixed steps (a lane with nothing to
+// move uses an offset past the buffer's extent: its load returns 0 and its
+// store is dropped).  The waits for them then count exactly, and no wait
+// covers another access still in flight -- a load issued under a divergent
+// branch, or a store every few symbols, would make every refill wait for
+// all of them.
+//   * input: each lane's next words wait in an LDS ring of LS_RING words, fed
+//     every LS_PERIOD steps from two sets of four word loads, each set in
+//     flight for two periods; a lane whose ring is empty before its chunk's
+//     words are all in skips the step;
+//   * output: every fourth symbol's word goes to an LDS ring of LS_OUT words;
+//     every LS_FLUSH steps the wave writes all lanes' new words, LS_OUT
+//     consecutive words of a chunk per group of lanes of a store instruction.
+constexpr int LS_RING = 16;
+constexpr int LS_RP = LS_RING + 1;  // odd pitches: lanes on different banks
+constexpr int LS_OUT = 16;
+constexpr int LS_OP = LS_OUT + 1;
+constexpr int LS_PERIOD = 8;
+constexpr int LS_FLUSH = 4 * LS_OUT;  // steps between flushes (at most LS_OUT words a lane)
+constexpr uint32_t LS_OOR = 0xFFFFFFF0u;  // an offset past every buffer's extent
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t ls_rsrc(const void *base, uint32_t bytes)
+{
+    // raw buffer (stride 0): accesses at or past `bytes` read 0 and drop writes
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t ls_load(rsrc_t r, uint32_t off)
+{
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+__device__ __forceinline__ uint64_t ls_min(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+struct LsSet {
+    uint32_t v[4];
+    uint32_t n;  // words of this set that carry data
+};
+
 __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__restrict__ payload,
                                                              uint64_t payload_bytes,
                                                              const uint64_t *__restrict__ offs,
@@ -249,124 +279,148 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
                                                              uint64_t raw, uint8_t *out, uint32_t *status)
 {
     __shared__ uint16_t s_tab[1u << MAXLEN];
+    __shared__ uint32_t s_in[DEC_THREADS * LS_RP];
+    __shared__ uint32_t s_out[DEC_THREADS * LS_OP];
+    __shared__ uint32_t s_from[DEC_THREADS], s_to[DEC_THREADS];
     for (uint32_t k = threadIdx.x; k < (1u << MAXLEN); k += DEC_THREADS)
         s_tab[k] = table[k];
-    __syncthreads();
-    const uint64_t c = (uint64_t)blockIdx.x * DEC_THREADS + threadIdx.x;
-    if (c >= nchunks)
-        return;
-    const uint64_t o0 = offs[c], o1 = offs[c + 1];
-    if (o1 < o0 || o1 > payload_bytes || (o0 | o1) % 4) {
-        atomicOr(status, czk::STATUS_FORMAT);
-        return;
+    const uint32_t lane = threadIdx.x;
+    const uint64_t c0 = (uint64_t)blockIdx.x * DEC_THREADS;
+    const uint64_t c = c0 + lane;
+    bool err = false;
+    bool live = c < nchunks;
+    uint64_t o0 = 0, o1 = 0;
+    if (live) {
+        o0 = offs[c];
+        o1 = offs[c + 1];
+        if (o1 < o0 || o1 > payload_bytes || (o0 | o1) % 4 || o1 == o0) {
+            err = true;  // a chunk with symbols needs words inside the payload
+            live = false;
+        }
     }
-    const uint64_t start = c * CHUNK;
-    const uint32_t n = (uint32_t)min<uint64_t>(CHUNK, raw - start);  // >= 1 for c < nchunks
-    if (o1 == o0) {
-        atomicOr(status, czk::STATUS_FORMAT);  // symbols but no bits
-        return;
+    // the workgroup's input window: from the smallest chunk start
+    uint64_t base = live ? o0 : ~0ull;
+#pragma unroll
+    for (int m = 1; m < DEC_THREADS; m <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)base, m, DEC_THREADS);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(base >> 32), m, DEC_THREADS);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        base = o < base ? o : base;
     }
-    const uint32_t nbits = (uint32_t)min<uint64_t>((o1 - o0) * 8, 1u << 31);  // a chunk needs < 2^16
-    const uint4 *pb = reinterpret_cast<const uint4 *>(payload);  // 16-byte aligned
-    const uint32_t *pw = reinterpret_cast<const uint32_t *>(payload);
-    const uint64_t nblk = payload_bytes / 16, nwords = payload_bytes / 4;
-    auto block = [&](uint64_t bi) -> uint4 {
-        if (bi < nblk)
-            return pb[bi];
-        uint4 v{0u, 0u, 0u, 0u};  // the payload's partial last block, zeros past its end
-        const uint64_t w = bi * 4;
-        if (w < nwords)
-            v.x = pw[w];
-        if (w + 1 < nwords)
-            v.y = pw[w + 1];
-        if (w + 2 < nwords)
-            v.z = pw[w + 2];
-        return v;
+    if (base == ~0ull)
+        base = 0;
+    {  // equal on every lane: make it scalar (readfirstlane returns a signed 32-bit value)
+        const uint32_t bhi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+        const uint32_t blo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
+        base = ((uint64_t)bhi << 32) | blo;
+    }
+    if (live && o1 - base > 0x7FFFFFF0ull) {  // a valid container's group spans a few hundred KiB
+        err = true;
+        live = false;
+    }
+    const rsrc_t rin = ls_rsrc(payload + base, (uint32_t)(ls_min(payload_bytes - base, 0x7FFFFFF0ull) & ~3ull));
+    const uint64_t obase = c0 * CHUNK;
+    const rsrc_t rout = ls_rsrc(out + obase, (uint32_t)(ls_min(raw - obase, (uint64_t)DEC_THREADS * CHUNK) & ~3ull));
+    const uint32_t w0 = live ? (uint32_t)((o0 - base) / 4) : 0u;  // first word, in the window
+    const uint32_t nw = live ? (uint32_t)((o1 - o0) / 4) : 0u;    // the chunk's words
+    const uint32_t nbits = nw * 32u;
+    const uint32_t n = live ? (uint32_t)ls_min(CHUNK, raw - c * CHUNK) : 0u;
+    uint32_t issued = 0, tail = 0, head = 0;
+    auto issue = [&](LsSet &s) {
+        s.n = (issued < nw && issued + 4 <= head + LS_RING) ? min(4u, nw - issued) : 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            s.v[k] = ls_load(rin, (uint32_t)k < s.n ? (w0 + issued + (uint32_t)k) * 4u : LS_OOR);
+        issued += s.n;
     };
+    uint32_t nxt = 0;  // the ring's word at head, once head < tail
+    auto land = [&](const LsSet &s) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if ((uint32_t)k < s.n)
+                s_in[lane * LS_RP + (tail + (uint32_t)k) % LS_RING] = s.v[k];
+        if (head == tail && s.n)
+            nxt = s.v[0];
+        tail += s.n;
+    };
+    LsSet A, B;
+    issue(A);
+    issue(B);
+    land(A);
+    land(B);
+    issue(A);
+    issue(B);
+    __syncthreads();  // the table
+
     uint64_t window = 0;
-    uint32_t avail = 0, used = 0, pack = 0, i = 0;
-    uint32_t *o32 = reinterpret_cast<uint32_t *>(out + start);
-    // decode one symbol from the window (at least MAXLEN bits in it); false on a bad code
-    auto one = [&]() -> bool {
-        const uint16_t e = s_tab[window & ((1u << MAXLEN) - 1)];
-        const uint32_t l = e >> 8;
-        used += l;
-        if (l == 0 || used > nbits)  // no such code, or past the chunk's bits
-            return false;
-        window >>= l;
-        avail -= l;
-        pack |= (uint32_t)(e & 0xFF) << (8 * (i % 4));
-        if (i % 4 == 3) {
-            o32[i / 4] = pack;
-            pack = 0;
+    uint32_t avail = 0, used = 0, pack = 0, i = 0, flushed = 0;
+    auto step = [&]() {
+        const bool go = live && i < n;
+        if (go && avail < (uint32_t)MAXLEN && head < tail) {
+            window |= (uint64_t)nxt << avail;
+            avail += 32;
+            ++head;
+            nxt = s_in[lane * LS_RP + head % LS_RING];  // needed two steps later at the earliest
         }
-        ++i;
-        return true;
+        // decode unless more words are due than have landed
+        if (go && (avail >= (uint32_t)MAXLEN || tail == nw)) {
+            const uint16_t e = s_tab[window & ((1u << MAXLEN) - 1)];
+            const uint32_t l = e >> 8;
+            used += l;
+            if (l == 0 || used > nbits) {  // no such code, or past the chunk's bits
+                err = true;
+                live = false;
+            } else {
+                window >>= l;
+                avail -= l;
+                pack |= (uint32_t)(e & 0xFF) << (8 * (i % 4));
+                if (i % 4 == 3) {
+                    s_out[lane * LS_OP + (i / 4) % LS_OUT] = pack;
+                    pack = 0;
+                }
+                ++i;
+            }
+        }
     };
-    if constexpr (FLAT) {
-        uint64_t bi = o0 / 16;
-        uint32_t wi = (uint32_t)(o0 / 4) % 4;  // next word of cur
-        uint4 cur = block(bi), n1 = block(bi + 1), n2 = block(bi + 2);
-        while (i < n) {
-            if (avail < (uint32_t)MAXLEN) {
-                const uint32_t w = wi == 0 ? cur.x : wi == 1 ? cur.y : wi == 2 ? cur.z : cur.w;
-                window |= (uint64_t)w << avail;
-                avail += 32;
-                if (++wi == 4) {
-                    wi = 0;
-                    cur = n1;
-                    n1 = n2;
-                    n2 = block(++bi + 2);
-                }
-            }
-            if (!one()) {
-                atomicOr(status, czk::STATUS_FORMAT);
-                return;
-            }
+    auto flush = [&]() {
+        // rows r: words [s_from[r], s_to[r]) of chunk c0 + r, 32 a row at most
+        s_from[lane] = flushed;
+        s_to[lane] = i / 4;
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < DEC_THREADS * LS_OUT / 64; ++k) {
+            const uint32_t r = (64u / LS_OUT) * (uint32_t)k + lane / LS_OUT;
+            const uint32_t w = s_from[r] + lane % LS_OUT;
+            const bool ok = w < s_to[r];
+            const uint32_t v = s_out[r * LS_OP + w % LS_OUT];
+            __builtin_amdgcn_raw_buffer_store_b32(v, rout, ok ? r * CHUNK + w * 4u : LS_OOR, 0, 0);
         }
-    } else {
-        const uint64_t b0 = o0 / 16;     // block holding the chunk's first word
-        int skip = (int)((o0 / 4) % 4);  // words of that block before the chunk
-        uint4 cur[GB], nxt[GB];
+        flushed = i / 4;
+        __syncthreads();
+    };
+    uint32_t s = 0;
+    while (__ballot(live && i < n)) {
 #pragma unroll
-        for (int k = 0; k < GB; ++k)
-            cur[k] = block(b0 + k);
+        for (int k = 0; k < LS_PERIOD; ++k)
+            step();
+        land(A);
+        issue(A);
 #pragma unroll
-        for (int k = 0; k < GB; ++k)
-            nxt[k] = block(b0 + GB + k);
-        uint64_t g = 0;
-        while (i < n) {
-#pragma unroll
-            for (int k = 0; k < 4 * GB; ++k) {
-                if (k < skip)
-                    continue;
-                if (i >= n)
-                    break;
-                const uint4 v = cur[k / 4];
-                const uint32_t w = k % 4 == 0 ? v.x : k % 4 == 1 ? v.y : k % 4 == 2 ? v.z : v.w;
-                window |= (uint64_t)w << avail;  // avail < MAXLEN here
-                avail += 32;
-                while (avail >= (uint32_t)MAXLEN && i < n) {
-                    if (!one()) {
-                        atomicOr(status, czk::STATUS_FORMAT);
-                        return;
-                    }
-                }
-            }
-            skip = 0;
-            // the next group becomes current; the one after it is requested
-            ++g;
-#pragma unroll
-            for (int k = 0; k < GB; ++k)
-                cur[k] = nxt[k];
-#pragma unroll
-            for (int k = 0; k < GB; ++k)
-                nxt[k] = block(b0 + (g + 1) * GB + k);
-        }
+        for (int k = 0; k < LS_PERIOD; ++k)
+            step();
+        land(B);
+        issue(B);
+        s += 2 * LS_PERIOD;
+        if (s % LS_FLUSH == 0)
+            flush();
     }
-    if (n % 4)
+    flush();
+    // the last chunk's trailing bytes
+    if (live && n % 4)
         for (uint32_t k = 0; k < n % 4; ++k)
-            out[start + n - n % 4 + k] = (uint8_t)(pack >> (8 * k));
+            out[c * CHUNK + n - n % 4 + k] = (uint8_t)(pack >> (8 * k));
+    if (err)
+        atomicOr(status, czk::STATUS_FORMAT);
 }
 
 // Package-merge: length-limited optimal code lengths (see the file header).
@@ -611,14 +665,9 @@ int cz_huff_decode(cz_ctx *ctx, const void *d_in, size_t in_bytes, void *d_out, 
     const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + HEAD);
     const uint16_t *tab = static_cast<const uint16_t *>(ctx->huff_stage.dev.ptr);
     uint8_t *dst = static_cast<uint8_t *>(d_out);
-    // mean code length from the payload size: short codes take the flat loop
     const dim3 grid((unsigned)((nchunks + DEC_THREADS - 1) / DEC_THREADS)), threads(DEC_THREADS);
-    if (pbytes * 8 < 4 * raw)
-        hipLaunchKernelGGL(decode_kernel<true>, grid, threads, 0, st, payload, pbytes, offs, tab, nchunks, raw, dst,
-                           &ctx->work->status);
-    else
-        hipLaunchKernelGGL(decode_kernel<false>, grid, threads, 0, st, payload, pbytes, offs, tab, nchunks, raw, dst,
-                           &ctx->work->status);
+    hipLaunchKernelGGL(decode_kernel, grid, threads, 0, st, payload, pbytes, offs, tab, nchunks, raw, dst,
+                       &ctx->work->status);
     return hipGetLastError() == hipSuccess ? CZ_OK : CZ_ERR_HIP;
 }
 

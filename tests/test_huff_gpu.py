@@ -47,8 +47,8 @@ def shuffled_stream(codec, seed):
 
 def inputs(codec):
     """Short codes (under 4 bits a byte: one symbol, two symbols, geometric,
-    Fibonacci) take the decoder's one-symbol-a-step loop; the others its
-    word-group loop."""
+    Fibonacci: a lane's words last many steps) and long ones (uniform,
+    shuffled stream: a lane needs a new word every few steps)."""
     rng = np.random.default_rng(5)
     yield "empty", np.zeros(0, np.uint8)
     yield "one byte", np.array([200], np.uint8)
@@ -167,7 +167,7 @@ def test_huffman_errors(codec):
     torch.cuda.synchronize()
     assert codec.status() == _cz.ERR_FORMAT
     assert codec.status() == 0
-    # the same for long codes (8 bits a byte: the word-group decoder)
+    # the same for long codes (8 bits a byte)
     wide = np.random.default_rng(3).integers(0, 256, 3 * CHUNK + 5, dtype=np.uint8)
     wblob = huffman.encode(wide.tobytes())
     d = torch.frombuffer(bytearray(wblob), dtype=torch.uint8).cuda()
@@ -178,3 +178,19 @@ def test_huffman_errors(codec):
     out = decode(blob)
     torch.cuda.synchronize()
     assert codec.status() == 0 and out[: host.size].cpu().numpy().tobytes() == host.tobytes()
+
+
+def test_round_trip_past_4_gib(codec):
+    """A container whose chunk offsets pass 2^31 and 2^32 bytes (4.4 GiB of
+    uniform bytes, 8-bit codes): decoding gives back every byte, so the
+    decoder's 64-bit payload positions hold past the 32-bit ranges."""
+    n = 4400 * 2 ** 20 + 3
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    dev = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=gen)
+    out, nb = codec.huff_encode(dev, n)
+    assert nb > 2 ** 32
+    back = codec.huff_decode(out, nb, n)
+    torch.cuda.synchronize()
+    assert codec.status() == 0
+    assert torch.equal(back[:n], dev)
+    say(f"[huff] 4.4 GiB round trip: container {nb} bytes")
