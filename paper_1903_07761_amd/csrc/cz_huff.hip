@@ -97,6 +97,14 @@ __global__ __launch_bounds__(HIST_THREADS) void hist_kernel(const uint8_t *__res
 // offset in the payload; its chunks are then copied out whole, back to back.
 constexpr int CPG = 8;
 
+// WORDS: the input is 16-byte aligned, and every thread reads its 16 bytes
+// of each chunk through a buffer resource whose extent is the group's input
+// rounded up to 16 bytes (a read is wholly inside it or wholly past it and
+// then reads 0; bytes past the input lie in its last 16-byte block, on its
+// last page, and are not used), issued by every thread for every chunk
+// before any is used -- all eight chunks' reads in flight together.
+// Otherwise 16-byte loads where aligned, bytes elsewhere.
+template <bool WORDS>
 __global__ __launch_bounds__(ENC_THREADS) void encode_kernel(const uint8_t *__restrict__ in, uint64_t n,
                                                              const uint32_t *__restrict__ code, uint64_t nchunks,
                                                              uint64_t *flags, uint32_t *ticket, uint64_t *offs,
@@ -127,20 +135,38 @@ __global__ __launch_bounds__(ENC_THREADS) void encode_kernel(const uint8_t *__re
     for (int j = 0; j < CPG; ++j) {
         const uint64_t base = (c0 + j) * CHUNK + (uint64_t)threadIdx.x * BYTES_PER_THREAD;
         cnt[j] = j < nc ? (int)min<uint64_t>(BYTES_PER_THREAD, base < n ? n - base : 0) : 0;
-        if (cnt[j] == BYTES_PER_THREAD && (reinterpret_cast<uintptr_t>(in + base) & 15) == 0) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(in + base);
-            data[j][0] = v.x;
-            data[j][1] = v.y;
-            data[j][2] = v.z;
-            data[j][3] = v.w;
-        } else {
+    }
+    if constexpr (WORDS) {
+        const uint64_t gbase = c0 * CHUNK;  // < n: the group has a chunk
+        const uint64_t span = min<uint64_t>(n - gbase, (uint64_t)CPG * CHUNK);
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t *>(in + gbase), (short)0, (int)((span + 15) & ~15ull), 0x00020000);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint32_t w = 0;
+        for (int j = 0; j < CPG; ++j)
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    w |= (4 * q + k < cnt[j] ? (uint32_t)in[base + 4 * q + k] : 0u) << (8 * k);
-                data[j][q] = w;
+            for (int q = 0; q < 4; ++q)
+                data[j][q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                    r, (uint32_t)(j * CHUNK + threadIdx.x * BYTES_PER_THREAD + 4 * q), 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < CPG; ++j) {
+        if constexpr (!WORDS) {
+            const uint64_t base = (c0 + j) * CHUNK + (uint64_t)threadIdx.x * BYTES_PER_THREAD;
+            if (cnt[j] == BYTES_PER_THREAD && (reinterpret_cast<uintptr_t>(in + base) & 15) == 0) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(in + base);
+                data[j][0] = v.x;
+                data[j][1] = v.y;
+                data[j][2] = v.z;
+                data[j][3] = v.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        w |= (4 * q + k < cnt[j] ? (uint32_t)in[base + 4 * q + k] : 0u) << (8 * k);
+                    data[j][q] = w;
+                }
             }
         }
         uint32_t bits = 0;
@@ -587,10 +613,16 @@ int cz_huff_encode(cz_ctx *ctx, const void *d_in, size_t nbytes, void *d_out, si
         return CZ_ERR_HIP;
     uint64_t *offs = reinterpret_cast<uint64_t *>(out + HEAD);
     if (nchunks) {
-        hipLaunchKernelGGL(encode_kernel, dim3((unsigned)ngroups), dim3(ENC_THREADS), 0, st, in, (uint64_t)nbytes,
-                           code, nchunks, reinterpret_cast<uint64_t *>(w + W_FLAGS),
-                           reinterpret_cast<uint32_t *>(w + W_TICKET), offs, out + p0, total,
-                           reinterpret_cast<uint32_t *>(w + W_STATUS));
+        if (reinterpret_cast<uintptr_t>(in) % 16 == 0)
+            hipLaunchKernelGGL(encode_kernel<true>, dim3((unsigned)ngroups), dim3(ENC_THREADS), 0, st, in,
+                               (uint64_t)nbytes, code, nchunks, reinterpret_cast<uint64_t *>(w + W_FLAGS),
+                               reinterpret_cast<uint32_t *>(w + W_TICKET), offs, out + p0, total,
+                               reinterpret_cast<uint32_t *>(w + W_STATUS));
+        else
+            hipLaunchKernelGGL(encode_kernel<false>, dim3((unsigned)ngroups), dim3(ENC_THREADS), 0, st, in,
+                               (uint64_t)nbytes, code, nchunks, reinterpret_cast<uint64_t *>(w + W_FLAGS),
+                               reinterpret_cast<uint32_t *>(w + W_TICKET), offs, out + p0, total,
+                               reinterpret_cast<uint32_t *>(w + W_STATUS));
         if (hipGetLastError() != hipSuccess)
             return CZ_ERR_HIP;
     } else if (hipMemsetAsync(offs, 0, 8, st) != hipSuccess) {

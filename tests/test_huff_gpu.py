@@ -74,6 +74,24 @@ def test_encode_matches_oracle(codec):
         say(f"[huff] encode {name}: {host.size} -> {n} bytes ok")
 
 
+def test_encode_misaligned_inputs_match_oracle(codec):
+    """Inputs that do not start on a 16-byte boundary take the encoder's
+    byte-wise path: the containers are still the oracle's."""
+    from oracle import huffman
+
+    rng = np.random.default_rng(9)
+    for shift in (1, 4, 8):
+        for size in (1, 3 * CHUNK + 77, 9 * CHUNK):
+            host = np.minimum(rng.geometric(0.2, size), 255).astype(np.uint8)
+            buf = torch.zeros(size + 16, dtype=torch.uint8, device="cuda")
+            buf[shift:shift + size] = torch.from_numpy(host).cuda()
+            view = buf[shift:shift + size]
+            assert view.data_ptr() % 16 != 0
+            out, n = codec.huff_encode(view, size)
+            assert out[:n].cpu().numpy().tobytes() == huffman.encode(host.tobytes()), (shift, size)
+    say("[huff] misaligned encode inputs ok")
+
+
 def test_decode_oracle_containers(codec):
     from oracle import huffman
 
