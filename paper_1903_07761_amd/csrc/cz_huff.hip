@@ -361,12 +361,11 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
     };
     uint32_t nxt = 0;  // the ring's word at head, once head < tail
     auto land = [&](const LsSet &s) {
+        // words past the set's count go to the row's pad word
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if ((uint32_t)k < s.n)
-                s_in[lane * LS_RP + (tail + (uint32_t)k) % LS_RING] = s.v[k];
-        if (head == tail && s.n)
-            nxt = s.v[0];
+            s_in[lane * LS_RP + ((uint32_t)k < s.n ? (tail + (uint32_t)k) % LS_RING : LS_RING)] = s.v[k];
+        nxt = head == tail && s.n ? s.v[0] : nxt;
         tail += s.n;
     };
     LsSet A, B;
@@ -380,33 +379,34 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
 
     uint64_t window = 0;
     uint32_t avail = 0, used = 0, pack = 0, i = 0, flushed = 0;
+    // one step, without branches: the lanes of a wavefront run one
+    // instruction stream, and a branch per condition would cost every lane
+    // the exec-mask bookkeeping of all of them
     auto step = [&]() {
         const bool go = live && i < n;
-        if (go && avail < (uint32_t)MAXLEN && head < tail) {
-            window |= (uint64_t)nxt << avail;
-            avail += 32;
-            ++head;
-            nxt = s_in[lane * LS_RP + head % LS_RING];  // needed two steps later at the earliest
-        }
+        const bool need = go && avail < (uint32_t)MAXLEN && head < tail;
+        window |= need ? (uint64_t)nxt << avail : 0ull;  // avail < 44: the shift is defined
+        avail += need ? 32u : 0u;
+        head += need ? 1u : 0u;
+        const uint32_t ahead = s_in[lane * LS_RP + head % LS_RING];  // needed two steps later at the earliest
+        nxt = need ? ahead : nxt;
         // decode unless more words are due than have landed
-        if (go && (avail >= (uint32_t)MAXLEN || tail == nw)) {
-            const uint16_t e = s_tab[window & ((1u << MAXLEN) - 1)];
-            const uint32_t l = e >> 8;
-            used += l;
-            if (l == 0 || used > nbits) {  // no such code, or past the chunk's bits
-                err = true;
-                live = false;
-            } else {
-                window >>= l;
-                avail -= l;
-                pack |= (uint32_t)(e & 0xFF) << (8 * (i % 4));
-                if (i % 4 == 3) {
-                    s_out[lane * LS_OP + (i / 4) % LS_OUT] = pack;
-                    pack = 0;
-                }
-                ++i;
-            }
-        }
+        const bool dec = go && (avail >= (uint32_t)MAXLEN || tail == nw);
+        const uint32_t e = s_tab[window & ((1u << MAXLEN) - 1)];
+        const uint32_t l = e >> 8;
+        const bool bad = dec && (l == 0 || used + l > nbits);  // no such code, or past the chunk's bits
+        const bool ok = dec && !bad;
+        err = err || bad;
+        live = live && !bad;
+        used += ok ? l : 0u;
+        window = ok ? window >> l : window;
+        avail -= ok ? l : 0u;
+        pack |= ok ? (e & 0xFFu) << (8 * (i % 4)) : 0u;
+        // a completed word goes to the ring, anything else to the row's pad word
+        const bool full = ok && i % 4 == 3;
+        s_out[lane * LS_OP + (full ? (i / 4) % LS_OUT : LS_OUT)] = pack;
+        pack = full ? 0u : pack;
+        i += ok ? 1u : 0u;
     };
     auto flush = [&]() {
         // rows r: words [s_from[r], s_to[r]) of chunk c0 + r, 32 a row at most
