@@ -251,9 +251,11 @@ __global__ __launch_bounds__(ENC_THREADS) void encode_kernel(const uint8_t *__re
     }
 }
 
-constexpr int DEC_THREADS = 64;  // one wavefront: a short stream has few chunks, and the
-                                 // lanes' lockstep below is the wavefront's
-static_assert(DEC_THREADS == 64, "the decoder's workgroup is one wavefront");
+// Decoder workgroups: one wavefront for short streams (few chunks: every
+// CU should get some), four for long ones (they share one copy of the table
+// in LDS, so more wavefronts fit a CU).  Each wavefront runs its own lockstep
+// loop and synchronizes only within itself.
+constexpr uint64_t DEC_WIDE_CHUNKS = 256ull * 64 * 16;  // chunks from which a group has four wavefronts
 
 // Decoding: one thread a chunk, table[k] = symbol | length << 8 for the next
 // 12 bits k (in LDS), one symbol a step on every lane, and every vector
@@ -267,16 +269,15 @@ static_assert(DEC_THREADS == 64, "the decoder's workgroup is one wavefront");
 //     every LS_PERIOD steps from two sets of four word loads, each set in
 //     flight for two periods; a lane whose ring is empty before its chunk's
 //     words are all in skips the step;
-//   * output: every fourth symbol's word goes to an LDS ring of LS_OUT words;
-//     every LS_FLUSH steps the wave writes all lanes' new words, LS_OUT
-//     consecutive words of a chunk per group of lanes of a store instruction.
+//   * output: every fourth symbol's word goes to an LDS ring of out_words
+//     words; every 4 out_words steps the wave writes all lanes' new words,
+//     out_words consecutive words of a chunk per group of lanes of a store
+//     instruction.
 constexpr int LS_RING = 16;
 constexpr int LS_RP = LS_RING + 1;  // odd pitches: lanes on different banks
-constexpr int LS_OUT = 16;
-constexpr int LS_OP = LS_OUT + 1;
 constexpr int LS_PERIOD = 8;
-constexpr int LS_FLUSH = 4 * LS_OUT;  // steps between flushes (at most LS_OUT words a lane)
 constexpr uint32_t LS_OOR = 0xFFFFFFF0u;  // an offset past every buffer's extent
+constexpr int out_words(int waves) { return waves > 1 ? 8 : 16; }
 
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
@@ -298,20 +299,40 @@ struct LsSet {
     uint32_t n;  // words of this set that carry data
 };
 
-__global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__restrict__ payload,
+// Ordering of LDS accesses between the lanes of one wavefront: they run in
+// program order, so a compiler-level fence suffices.  A one-wavefront group
+// uses the workgroup barrier, which is the same there and compiles tighter.
+template <int WAVES>
+__device__ __forceinline__ void wave_sync()
+{
+    if constexpr (WAVES == 1) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void decode_kernel(const uint8_t *__restrict__ payload,
                                                              uint64_t payload_bytes,
                                                              const uint64_t *__restrict__ offs,
                                                              const uint16_t *__restrict__ table, uint64_t nchunks,
                                                              uint64_t raw, uint8_t *out, uint32_t *status)
 {
+    constexpr int NT = 64 * WAVES;
+    constexpr int LS_OUT = out_words(WAVES), LS_OP = LS_OUT + 1, LS_FLUSH = 4 * LS_OUT;
     __shared__ uint16_t s_tab[1u << MAXLEN];
-    __shared__ uint32_t s_in[DEC_THREADS * LS_RP];
-    __shared__ uint32_t s_out[DEC_THREADS * LS_OP];
-    __shared__ uint32_t s_from[DEC_THREADS], s_to[DEC_THREADS];
-    for (uint32_t k = threadIdx.x; k < (1u << MAXLEN); k += DEC_THREADS)
+    __shared__ uint32_t s_in[NT * LS_RP];  // a row per thread
+    __shared__ uint32_t s_out[NT * LS_OP];
+    __shared__ uint32_t s_from[NT], s_to[NT];
+    for (uint32_t k = threadIdx.x; k < (1u << MAXLEN); k += NT)
         s_tab[k] = table[k];
-    const uint32_t lane = threadIdx.x;
-    const uint64_t c0 = (uint64_t)blockIdx.x * DEC_THREADS;
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = WAVES > 1 ? t % 64 : t;
+    const uint32_t w64 = WAVES > 1 ? t - lane : 0u;  // the wavefront's first thread
+    const uint64_t c0 = ((uint64_t)blockIdx.x * WAVES + t / 64) * 64;  // the wavefront's first chunk
     const uint64_t c = c0 + lane;
     bool err = false;
     bool live = c < nchunks;
@@ -327,9 +348,9 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
     // the workgroup's input window: from the smallest chunk start
     uint64_t base = live ? o0 : ~0ull;
 #pragma unroll
-    for (int m = 1; m < DEC_THREADS; m <<= 1) {
-        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)base, m, DEC_THREADS);
-        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(base >> 32), m, DEC_THREADS);
+    for (int m = 1; m < 64; m <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)base, m, 64);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(base >> 32), m, 64);
         const uint64_t o = ((uint64_t)hi << 32) | lo;
         base = o < base ? o : base;
     }
@@ -345,8 +366,8 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
         live = false;
     }
     const rsrc_t rin = ls_rsrc(payload + base, (uint32_t)(ls_min(payload_bytes - base, 0x7FFFFFF0ull) & ~3ull));
-    const uint64_t obase = c0 * CHUNK;
-    const rsrc_t rout = ls_rsrc(out + obase, (uint32_t)(ls_min(raw - obase, (uint64_t)DEC_THREADS * CHUNK) & ~3ull));
+    const uint64_t obase = c0 * CHUNK;  // below raw unless the wavefront has no chunk (then unused)
+    const rsrc_t rout = ls_rsrc(out + obase, (uint32_t)(ls_min(raw - obase, 64ull * CHUNK) & ~3ull));
     const uint32_t w0 = live ? (uint32_t)((o0 - base) / 4) : 0u;  // first word, in the window
     const uint32_t nw = live ? (uint32_t)((o1 - o0) / 4) : 0u;    // the chunk's words
     const uint32_t nbits = nw * 32u;
@@ -364,7 +385,7 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
         // words past the set's count go to the row's pad word
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            s_in[lane * LS_RP + ((uint32_t)k < s.n ? (tail + (uint32_t)k) % LS_RING : LS_RING)] = s.v[k];
+            s_in[t * LS_RP + ((uint32_t)k < s.n ? (tail + (uint32_t)k) % LS_RING : LS_RING)] = s.v[k];
         nxt = head == tail && s.n ? s.v[0] : nxt;
         tail += s.n;
     };
@@ -375,7 +396,9 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
     land(B);
     issue(A);
     issue(B);
-    __syncthreads();  // the table
+    __syncthreads();  // the table; from here on each wavefront keeps to itself
+    if (c0 >= nchunks)
+        return;
 
     uint64_t window = 0;
     uint32_t avail = 0, used = 0, pack = 0, i = 0, flushed = 0;
@@ -388,7 +411,7 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
         window |= need ? (uint64_t)nxt << avail : 0ull;  // avail < 44: the shift is defined
         avail += need ? 32u : 0u;
         head += need ? 1u : 0u;
-        const uint32_t ahead = s_in[lane * LS_RP + head % LS_RING];  // needed two steps later at the earliest
+        const uint32_t ahead = s_in[t * LS_RP + head % LS_RING];  // needed two steps later at the earliest
         nxt = need ? ahead : nxt;
         // decode unless more words are due than have landed
         const bool dec = go && (avail >= (uint32_t)MAXLEN || tail == nw);
@@ -404,25 +427,26 @@ __global__ __launch_bounds__(DEC_THREADS) void decode_kernel(const uint8_t *__re
         pack |= ok ? (e & 0xFFu) << (8 * (i % 4)) : 0u;
         // a completed word goes to the ring, anything else to the row's pad word
         const bool full = ok && i % 4 == 3;
-        s_out[lane * LS_OP + (full ? (i / 4) % LS_OUT : LS_OUT)] = pack;
+        s_out[t * LS_OP + (full ? (i / 4) % LS_OUT : LS_OUT)] = pack;
         pack = full ? 0u : pack;
         i += ok ? 1u : 0u;
     };
     auto flush = [&]() {
-        // rows r: words [s_from[r], s_to[r]) of chunk c0 + r, 32 a row at most
-        s_from[lane] = flushed;
-        s_to[lane] = i / 4;
-        __syncthreads();
+        // rows r of the wavefront: words [s_from, s_to) of chunk c0 + r,
+        // LS_OUT a row at most
+        s_from[t] = flushed;
+        s_to[t] = i / 4;
+        wave_sync<WAVES>();
 #pragma unroll 4
-        for (int k = 0; k < DEC_THREADS * LS_OUT / 64; ++k) {
+        for (int k = 0; k < LS_OUT; ++k) {
             const uint32_t r = (64u / LS_OUT) * (uint32_t)k + lane / LS_OUT;
-            const uint32_t w = s_from[r] + lane % LS_OUT;
-            const bool ok = w < s_to[r];
-            const uint32_t v = s_out[r * LS_OP + w % LS_OUT];
+            const uint32_t w = s_from[w64 + r] + lane % LS_OUT;
+            const bool ok = w < s_to[w64 + r];
+            const uint32_t v = s_out[(w64 + r) * LS_OP + w % LS_OUT];
             __builtin_amdgcn_raw_buffer_store_b32(v, rout, ok ? r * CHUNK + w * 4u : LS_OOR, 0, 0);
         }
         flushed = i / 4;
-        __syncthreads();
+        wave_sync<WAVES>();
     };
     uint32_t s = 0;
     while (__ballot(live && i < n)) {
@@ -697,9 +721,12 @@ int cz_huff_decode(cz_ctx *ctx, const void *d_in, size_t in_bytes, void *d_out, 
     const uint64_t *offs = reinterpret_cast<const uint64_t *>(in + HEAD);
     const uint16_t *tab = static_cast<const uint16_t *>(ctx->huff_stage.dev.ptr);
     uint8_t *dst = static_cast<uint8_t *>(d_out);
-    const dim3 grid((unsigned)((nchunks + DEC_THREADS - 1) / DEC_THREADS)), threads(DEC_THREADS);
-    hipLaunchKernelGGL(decode_kernel, grid, threads, 0, st, payload, pbytes, offs, tab, nchunks, raw, dst,
-                       &ctx->work->status);
+    if (nchunks >= DEC_WIDE_CHUNKS)
+        hipLaunchKernelGGL(decode_kernel<4>, dim3((unsigned)((nchunks + 255) / 256)), dim3(256), 0, st, payload,
+                           pbytes, offs, tab, nchunks, raw, dst, &ctx->work->status);
+    else
+        hipLaunchKernelGGL(decode_kernel<1>, dim3((unsigned)((nchunks + 63) / 64)), dim3(64), 0, st, payload,
+                           pbytes, offs, tab, nchunks, raw, dst, &ctx->work->status);
     return hipGetLastError() == hipSuccess ? CZ_OK : CZ_ERR_HIP;
 }
 
