@@ -14,7 +14,8 @@
 //     z-slabs at a time (Z = N keeps a 32^3 float block whole in LDS; double
 //     blocks, 256 KiB at N = 32, are staged by slab), each line transformed
 //     in registers by one thread, then the z-lines in registers;
-//   * the coarser levels (at most (N/2)^3) run entirely in LDS;
+//   * the coarser levels (at most (N/2)^3): x- and y-lines in LDS, z-lines in
+//     the registers of the columns that hold them;
 //   * decimation: one wavefront ballot per 64 consecutive coefficients gives a
 //     mask word directly in the stream's bit order; word popcounts are scanned
 //     across the workgroup, and each kept value's rank is the word prefix plus
@@ -23,7 +24,7 @@
 //     (each block publishes its record size as soon as its nnz is known, then
 //     accumulates predecessors until it meets an inclusive prefix);
 //   * the inverse mirrors the forward: mask words to LDS, ranks by prefix
-//     popcount, gather, coarse levels in LDS, z-lines in registers, y and x
+//     popcount, gather, coarse levels, z-lines in registers, y and x
 //     lines by slab group through LDS, coalesced store.
 // The path is a short stencil plus a scan: bound by HBM bandwidth, no MFMA.
 #pragma clang fp contract(off)
@@ -135,32 +136,76 @@ __device__ __forceinline__ void lds_lines(T *lds)
     }
 }
 
-// Forward levels n, n/2, ..., 8 of the region [0,n)^3 held in LDS.
-template <typename T, int S, int n, int PY, int PZ>
-__device__ __forceinline__ void lds_levels_fwd(T *lds)
+// Forward levels n, n/2, ..., 8 of the coarse region [0, n)^3 (LDS pitches
+// PY, PZ), which is in LDS on entry: x- and y-lines in LDS, z-lines in the
+// registers of the columns' owners (the thread of column (x, y), x, y < n,
+// holds z in [0, n) in c[r], y = yq + r YR); on return the region's final
+// coefficients are in c.  Each level's z-lines need no LDS pass.
+template <typename T, int S, int n, int PY, int PZ, int R, int YR, int NC>
+__device__ __forceinline__ void coarse_fwd(T (&c)[R][NC], T *lds, int x, int yq)
 {
     lds_lines<T, S, n, 0, false, PY, PZ>(lds);
     lds_barrier();
     lds_lines<T, S, n, 1, false, PY, PZ>(lds);
     lds_barrier();
-    lds_lines<T, S, n, 2, false, PY, PZ>(lds);
-    lds_barrier();
-    if constexpr (n / 2 >= 8)
-        lds_levels_fwd<T, S, n / 2, PY, PZ>(lds);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = yq + r * YR;
+        if (r * YR < n && x < n && y < n) {
+#pragma unroll
+            for (int z = 0; z < n; ++z)
+                c[r][z] = lds[z * PZ + y * PY + x];
+            line_fwd<T, S, n>(c[r]);
+        }
+    }
+    if constexpr (n / 2 >= 8) {
+        // the next level's region back to LDS (each owner its own column)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = yq + r * YR;
+            if (r * YR < n / 2 && x < n / 2 && y < n / 2) {
+#pragma unroll
+                for (int z = 0; z < n / 2; ++z)
+                    lds[z * PZ + y * PY + x] = c[r][z];
+            }
+        }
+        lds_barrier();
+        coarse_fwd<T, S, n / 2, PY, PZ, R, YR, NC>(c, lds, x, yq);
+    }
 }
 
-// Inverse levels 8, 16, ..., n of the region [0,n)^3 held in LDS.
-template <typename T, int S, int n, int PY, int PZ>
-__device__ __forceinline__ void lds_levels_inv(T *lds)
+// Inverse levels 8, 16, ..., n of the coarse region [0, n)^3, which is in
+// the owners' registers on entry (as coarse_fwd leaves it) and on return:
+// each level's z-lines there, its y- and x-lines in LDS.
+template <typename T, int S, int n, int PY, int PZ, int R, int YR, int NC>
+__device__ __forceinline__ void coarse_inv(T (&c)[R][NC], T *lds, int x, int yq)
 {
     if constexpr (n / 2 >= 8)
-        lds_levels_inv<T, S, n / 2, PY, PZ>(lds);
-    lds_lines<T, S, n, 2, true, PY, PZ>(lds);
+        coarse_inv<T, S, n / 2, PY, PZ, R, YR, NC>(c, lds, x, yq);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = yq + r * YR;
+        if (r * YR < n && x < n && y < n) {
+            line_inv<T, S, n>(c[r]);
+#pragma unroll
+            for (int z = 0; z < n; ++z)
+                lds[z * PZ + y * PY + x] = c[r][z];
+        }
+    }
     lds_barrier();
     lds_lines<T, S, n, 1, true, PY, PZ>(lds);
     lds_barrier();
     lds_lines<T, S, n, 0, true, PY, PZ>(lds);
     lds_barrier();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = yq + r * YR;
+        if (r * YR < n && x < n && y < n) {
+#pragma unroll
+            for (int z = 0; z < n; ++z)
+                c[r][z] = lds[z * PZ + y * PY + x];
+        }
+    }
 }
 
 template <typename T>
@@ -458,7 +503,7 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
     }
     __builtin_amdgcn_sched_barrier(0);
 
-    // coarser levels: [0, N/2)^3 in LDS (only columns with y < N/2 take part)
+    // coarser levels: [0, N/2)^3 (only columns with x, y < N/2 take part)
     if constexpr (N / 2 >= 8) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -472,20 +517,7 @@ __global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
             }
         }
         lds_barrier();
-        lds_levels_fwd<T, S, G::H, G::QX, G::QS>(lds);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (r * G::YR < G::H) {
-                const int y = yq + r * G::YR;
-                const bool in = x < G::H && y < G::H;
-                const int base = in ? y * G::QX + x : 0;
-#pragma unroll
-                for (int z = 0; z < G::H; ++z) {
-                    const T v = lds[z * G::QS + base];
-                    c[r][z] = in ? v : c[r][z];
-                }
-            }
-        }
+        coarse_fwd<T, S, G::H, G::QX, G::QS, R, G::YR, N>(c, lds, x, yq);
     }
 
     // decimation: keep the 4^3 corner and |c| >= eps (compared in double).
@@ -689,29 +721,10 @@ __global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
             }
         }
 
-        // coarser levels 8 .. N/2 in LDS
+        // coarser levels 8 .. N/2: z-lines in VGPRs, y- and x-lines in LDS
         if constexpr (N / 2 >= 8) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int y = yq + r * G::YR;
-                if (x < G::H && y < G::H) {
-#pragma unroll
-                    for (int z = 0; z < G::H; ++z)
-                        lds[z * G::QS + y * G::QX + x] = c[r][z];
-                }
-            }
-            lds_barrier();
-            lds_levels_inv<T, S, G::H, G::QX, G::QS>(lds);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int y = yq + r * G::YR;
-                if (x < G::H && y < G::H) {
-#pragma unroll
-                    for (int z = 0; z < G::H; ++z)
-                        c[r][z] = lds[z * G::QS + y * G::QX + x];
-                }
-            }
-            lds_barrier();
+            coarse_inv<T, S, G::H, G::QX, G::QS, R, G::YR, N>(c, lds, x, yq);
+            lds_barrier();  // the staging below reuses the coarse area
         }
 
         // finest level: z in VGPRs, then y- and x-lines per slab group
