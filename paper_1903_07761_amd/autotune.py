@@ -65,6 +65,19 @@ def _time_variant(codec, f, block, scheme, eps, reps):
     return statistics.median(fwd), statistics.median(inv), buf[:n].cpu().numpy().tobytes()
 
 
+# A variant replaces variant 0 only when its forward + inverse time is at
+# least this much lower: differences within run-to-run noise on the tuning
+# field do not carry over to other fields.
+MARGIN = 0.03
+
+
+def pick(totals) -> int:
+    """Index of the variant to use given forward + inverse milliseconds per
+    variant (index 0 the default)."""
+    best = min(range(len(totals)), key=lambda v: totals[v])
+    return best if totals[best] <= (1.0 - MARGIN) * totals[0] else 0
+
+
 def tune(codec, edge: int = 512, reps: int = 5, blocks=BLOCKS, elems=(4, 8), schemes=SCHEMES, log=print):
     """Time every variant of every (N, precision, scheme); return the table
     entry for this device: {key: {"variant", "fwd_ms", "inv_ms"}}."""
@@ -89,10 +102,10 @@ def tune(codec, edge: int = 512, reps: int = 5, blocks=BLOCKS, elems=(4, 8), sch
                         raise RuntimeError(f"variant {v} of {key(N, elem, s)} changed the stream")
                     res.append((tf + ti, v, tf, ti))
                     log(f"{key(N, elem, s)} variant {v}: fwd {tf:.3f} ms inv {ti:.3f} ms")
-                best = min(res)
+                res.sort(key=lambda r: r[1])
                 codec.ctx.set_variant(N, elem, s, 0)
-                out[key(N, elem, s)] = {"variant": best[1], "fwd_ms": [round(r[2], 4) for r in sorted(res, key=lambda r: r[1])],
-                                        "inv_ms": [round(r[3], 4) for r in sorted(res, key=lambda r: r[1])]}
+                out[key(N, elem, s)] = {"variant": pick([r[0] for r in res]), "fwd_ms": [round(r[2], 4) for r in res],
+                                        "inv_ms": [round(r[3], 4) for r in res]}
             del f
     return out
 
@@ -133,7 +146,7 @@ def main(argv=None):
     entries = tune(codec, edge=args.edge, reps=args.reps, log=log)
     table = load(args.out)
     table[arch] = {"field": f"bubble cloud of edge max({args.edge}, 8 N), eps 1e-3 of range", "reps": args.reps,
-                   "variants": entries}
+                   "margin": MARGIN, "variants": entries}
     with open(args.out, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     print(json.dumps({"arch": arch, "entries": len(entries)}))

@@ -433,8 +433,17 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // One workgroup per block: the block's ticket is taken at workgroup start,
 // so every smaller ticket belongs to a workgroup that is resident or done and
 // the look-back always completes.
+// Waves per SIMD the forward kernel's registers must leave room for: what
+// one workgroup implies, except for float 32^3 blocks with two columns a
+// thread and ZP = 18 (76 KiB of LDS), which run two workgroups a CU.
+template <typename T, int N, int Z, int R, int ZP>
+struct FwdWaves {
+    static constexpr int one = N * N / R / 256 > 0 ? N * N / R / 256 : 1;
+    static constexpr int value = sizeof(T) == 4 && N == 32 && Z == 16 && R == 2 && ZP == 18 ? 2 * one : one;
+};
+
 template <typename T, int N, int S, int Z, int R, int ZP>
-__global__ __launch_bounds__(N *N / R) void fwd_kernel(Queue q)
+__global__ __launch_bounds__(N *N / R, (FwdWaves<T, N, Z, R, ZP>::value)) void fwd_kernel(Queue q)
 {
     using G = Geom<T, N, Z, R, ZP>;
     __shared__ T lds[G::LDS_ELEMS];
@@ -1244,9 +1253,12 @@ __global__ void fold_status_kernel(const uint32_t *counters, int nclass, uint32_
 template <typename T, int N, int V>
 struct Shape {
     static constexpr bool big = sizeof(T) == 8 && N >= 32;
-    static constexpr int Z = (V == 1 && N >= 16) ? (big ? N / 4 : N / 2) : (big ? N / 2 : N);
-    static constexpr int R = (V == 2 && big) || (V == 1 && N == 32) ? 2 : 1;
-    static constexpr int ZP = N < 32 ? N : (big ? N / 2 + 2 : N / 2);
+    // float 32^3, variant 2: the variant-1 tiling with two planes fewer parked
+    // (76 KiB of LDS) so that two workgroups share a CU
+    static constexpr bool pair = !big && N == 32 && V == 2;
+    static constexpr int Z = (V == 1 && N >= 16) || pair ? (big ? N / 4 : N / 2) : (big ? N / 2 : N);
+    static constexpr int R = (V == 2 && big) || (V == 1 && N == 32) || pair ? 2 : 1;
+    static constexpr int ZP = N < 32 ? N : (big || pair ? N / 2 + 2 : N / 2);
     static constexpr int NT = N * N / R;
 };
 
@@ -1308,7 +1320,7 @@ static hipError_t scratch_dispatch(bool inverse, const Queue &q, int grid, hipSt
     if (key.variant == 1) {                                                                                  \
         CZ_SCHEMES(T, N, 1, OP, ARGS)                                                                        \
     }                                                                                                        \
-    if constexpr (sizeof(T) == 8 && N == 32) {                                                               \
+    if constexpr (N == 32) {                                                                                 \
         if (key.variant == 2) {                                                                              \
             CZ_SCHEMES(T, N, 2, OP, ARGS)                                                                    \
         }                                                                                                    \
@@ -1386,7 +1398,7 @@ bool fwd_one_block_per_workgroup(const KernelKey &key) { return key.block <= 32;
 int variant_count(uint32_t block, uint32_t elem_bytes)
 {
     if (block == 32)
-        return elem_bytes == 8 ? 3 : 2;
+        return 3;
     return block == 16 ? 2 : block == 64 ? 3 : 1;
 }
 

@@ -94,3 +94,38 @@ def test_huff_bound_matches_container_layout(czlib):
 
     data = np.random.default_rng(1).integers(0, 256, 3 * 4096 + 11, dtype=np.uint8).tobytes()
     assert len(huffman.encode(data)) <= czlib.huff_bound(len(data))
+
+
+def test_variant_counts(czlib):
+    """Tiling variants per block size (any precision): one for 8^3, two for
+    16^3, three for 32^3 and for 64^3 (resident scratch slots)."""
+    for elem in (4, 8):
+        assert [czlib.variant_count(n, elem) for n in (8, 16, 32, 64)] == [1, 2, 3, 3]
+
+
+def test_tuner_keeps_the_default_within_the_margin():
+    from paper_1903_07761_amd.autotune import MARGIN, pick
+
+    assert pick([1.0]) == 0
+    assert pick([1.0, 0.99, 1.2]) == 0  # 1% faster: noise, the default stays
+    assert pick([1.0, 1.1, 1.0 - 2 * MARGIN]) == 2
+    assert pick([1.0, 1.0 - 2 * MARGIN, 1.0 - 3 * MARGIN]) == 2
+    assert pick([0.5, 0.4, 0.45]) == 1
+
+
+def test_committed_table_follows_its_own_times(czlib):
+    """Every entry of the committed table names a variant that exists and is
+    the one the tuner's rule picks from the times recorded beside it."""
+    import json
+
+    from paper_1903_07761_amd.autotune import DEFAULT_TABLE, pick
+
+    with open(DEFAULT_TABLE) as fh:
+        table = json.load(fh)
+    assert table
+    for arch, rec in table.items():
+        for k, v in rec["variants"].items():
+            nkey, tkey, _ = k.split("/")
+            nv = czlib.variant_count(int(nkey[1:]), 4 if tkey == "f32" else 8)
+            assert len(v["fwd_ms"]) == len(v["inv_ms"]) == nv, k
+            assert v["variant"] == pick([a + b for a, b in zip(v["fwd_ms"], v["inv_ms"])]), (arch, k)
