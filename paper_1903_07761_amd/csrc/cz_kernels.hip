@@ -632,8 +632,17 @@ __global__ __launch_bounds__(N *N / R, (FwdWaves<T, N, Z, R, ZP>::value)) void f
 
 // ------------------------------------------------------------------ inverse
 
+// The same for the inverse: float 32^3 blocks with two columns a thread and
+// 16-slab staging (72 KiB of LDS) fit two workgroups a CU when the
+// registers do.
+template <typename T, int N, int Z, int R>
+struct InvWaves {
+    static constexpr int one = N * N / R / 256 > 0 ? N * N / R / 256 : 1;
+    static constexpr int value = sizeof(T) == 4 && N == 32 && Z == 16 && R == 2 ? 2 * one : one;
+};
+
 template <typename T, int N, int S, int Z, int R>
-__global__ __launch_bounds__(N *N / R) void inv_kernel(Queue q)
+__global__ __launch_bounds__(N *N / R, (InvWaves<T, N, Z, R>::value)) void inv_kernel(Queue q)
 {
     using G = Geom<T, N, Z, R>;
     __shared__ T lds[G::LDS_ELEMS];
