@@ -659,9 +659,25 @@ __global__ __launch_bounds__(N *N / R, (InvWaves<T, N, Z, R>::value)) void inv_k
     const uint32_t lane = lane_id();
     const int wave = tid / 64;
 
+    // Small blocks take their tickets TB at a time: they decode in well under
+    // a microsecond, and one atomic per block on the single counter (which
+    // the L2 serialises) would set the pace.  Any order is correct here:
+    // blocks are independent.  (The surplus grid x TB on the counter is far
+    // from its 32-bit range.)
+    constexpr uint32_t TB = N <= 8 ? 8 : N <= 16 ? 4 : 1;
+    uint32_t next = 0, end = 0;  // thread 0's batch [next, end)
     while (true) {
         if (tid == 0) {
-            const uint64_t t = atomicAdd(q.ticket, 1u);
+            uint64_t t;
+            if constexpr (TB == 1) {
+                t = atomicAdd(q.ticket, 1u);
+            } else {
+                if (next == end) {
+                    next = atomicAdd(q.ticket, TB);
+                    end = next + TB;
+                }
+                t = next++;
+            }
             uint32_t ok = 0, f = 0;
             uint64_t rb = 0, ob = 0;
             if (t < q.ntickets) {
