@@ -6,7 +6,8 @@ quantity at a time), so every batched output must be byte-identical to the
 single-field call with the same parameters, and that call is held to the
 oracle by the parity tests; one case here also goes straight to the oracle.
 Plans are replayed several times with eager work between the replays, each
-replay checked against the eager result.
+replay checked against the eager result and against the oracle; the batched
+forward and the batched inverse are also compared with the oracle directly.
 """
 import numpy as np
 import pytest
@@ -92,7 +93,7 @@ def test_compress_batch_async_sizes(codec):
 
 
 def test_batch_against_oracle(codec, oracle):
-    items = mixed_fields(7003)[:4]
+    items = mixed_fields(7003)
     outs, sizes = codec.compress_batch(*zip(*[(f, N, s, e) for f, N, s, e in items]))
     for (f, N, s, eps), o, n in zip(items, outs, sizes):
         ref = oracle.compress(f.cpu().numpy(), N, s, eps)
@@ -109,6 +110,22 @@ def test_decompress_batch_matches_single_calls(codec):
         one = codec.decompress(o, n)
         torch.cuda.synchronize()
         assert recs[i].cpu().numpy().tobytes() == one.cpu().numpy().tobytes()
+
+
+def test_decompress_batch_against_oracle(codec, oracle):
+    """The batched inverse of the oracle's streams equals the oracle's inverse."""
+    items = mixed_fields(7008)
+    ps = [codec.params(f, N, s, e) for f, N, s, e in items]
+    streams = [oracle.compress(f.cpu().numpy(), N, s, e) for f, N, s, e in items]
+    bufs = [torch.frombuffer(bytearray(o), dtype=torch.uint8).cuda() if o else torch.empty(0, dtype=torch.uint8,
+            device="cuda") for o in streams]
+    recs = codec.decompress_batch(bufs, [len(o) for o in streams], ps)
+    torch.cuda.synchronize()
+    assert codec.status() == 0
+    for i, (o, r) in enumerate(zip(streams, recs)):
+        want = oracle.decompress(o)
+        say(f"[batch inv vs oracle] field {i}: N={items[i][1]} {items[i][2]} {items[i][0].dtype}")
+        assert r.cpu().numpy().tobytes() == want.tobytes(), i
 
 
 def test_decompress_batch_reports_corrupt_stream(codec):
@@ -145,7 +162,7 @@ def test_compress_batch_nonfinite_and_capacity(codec):
     assert e.value.code == _cz.ERR_CAPACITY
 
 
-def test_plan_replays(codec):
+def test_plan_replays(codec, oracle):
     items = mixed_fields(7007)
     ps = [codec.params(f, N, s, e) for f, N, s, e in items]
     plan = codec.plan("compress", ps)
@@ -165,7 +182,10 @@ def test_plan_replays(codec):
         say(f"[plan] replay {rep}: sizes {sizes}")
         for i in range(len(items)):
             assert sizes[i] == len(ref[i])
-            assert bufs[i][: sizes[i]].cpu().numpy().tobytes() == ref[i], (rep, i)
+            got = bufs[i][: sizes[i]].cpu().numpy().tobytes()
+            assert got == ref[i], (rep, i)
+            f, N, s, eps = cur[i]
+            assert got == oracle.compress(f.cpu().numpy(), N, s, eps), ("oracle", rep, i)
         inv.run([b.data_ptr() for b in bufs], [r.data_ptr() for r in recs],
                 [r.numel() * r.element_size() for r in recs], src_bytes=sizes, stream=st)
         assert inv.result(stream=st) is None
@@ -173,6 +193,9 @@ def test_plan_replays(codec):
             one = codec.decompress(bufs[i], sizes[i])
             torch.cuda.synchronize()
             assert recs[i].cpu().numpy().tobytes() == one.cpu().numpy().tobytes(), (rep, i)
+            want = oracle.decompress(bufs[i][: sizes[i]].cpu().numpy().tobytes()) if sizes[i] else None
+            if want is not None:
+                assert recs[i].cpu().numpy().tobytes() == want.tobytes(), ("oracle", rep, i)
     plan.close()
     inv.close()
 
