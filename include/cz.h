@@ -81,7 +81,8 @@ enum {
     CZ_ERR_FORMAT = -5,    /* corrupt or inconsistent stream                   */
     CZ_ERR_HIP = -6,       /* HIP runtime failure                              */
     CZ_ERR_BUDGET = -7,    /* request larger than a server's memory budget     */
-    CZ_ERR_TIMEOUT = -8    /* a device-side wait exceeded its bound             */
+    CZ_ERR_TIMEOUT = -8,   /* a device-side wait exceeded its bound             */
+    CZ_ERR_SCRATCH = -9    /* beyond the fixed scratch of cz_compress_noalloc   */
 };
 
 typedef struct {
@@ -129,6 +130,26 @@ int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_ou
  * or more. */
 int cz_compress_strided(cz_ctx *ctx, const cz_params *p, const void *d_state, uint32_t ncomp, uint32_t comp,
                         void *d_out, size_t out_cap, uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cz_compress
+ * with no allocation of any kind.  The call's scratch -- its ticket, status
+ * and size words, its descriptor and one look-back flag per block -- lives in
+ * a fixed array in the library's device code (one copy per device, held until
+ * the process ends, located once per device by cz_create), never in the
+ * context's growable workspace.  Limits: N <= 32 and at most
+ * CZ_NOALLOC_MAX_BLOCKS blocks; anything larger returns CZ_ERR_SCRATCH before
+ * any work is issued (use cz_compress there).  Arguments, stream contents and
+ * the other returns are exactly those of cz_compress.  Synchronous when
+ * h_out_bytes != NULL (size and device error returned); otherwise the size
+ * goes to *d_out_bytes and the call's device error is folded into the
+ * context's status word, read with cz_get_status.  Every call on one device
+ * shares that device's array and starts by clearing it (with a kernel, not a
+ * memset): two calls that overlap in time on one device race, whatever their
+ * contexts or streams. */
+#define CZ_NOALLOC_MAX_BLOCKS 1048576u /* 2^20 blocks: 8 MiB of flags */
+int cz_compress_noalloc(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_out, size_t out_cap,
+                        uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream);
 
 /* Rebuild the field from the stream d_in (in_bytes long) into d_field
  * (field_cap bytes).  With expected == NULL the 64-byte header is read back

@@ -16,8 +16,9 @@ LIB_PATH = os.path.join(PKG, "libcz.so")
 W4, W4_LI, W3_AI = 0, 1, 2
 SCHEMES = {"W4": W4, "W4_li": W4_LI, "W3_ai": W3_AI}
 
-OK, ERR_ARG, ERR_SHAPE, ERR_CAPACITY, ERR_NONFINITE, ERR_FORMAT, ERR_HIP, ERR_BUDGET, ERR_TIMEOUT = (
-    0, -1, -2, -3, -4, -5, -6, -7, -8)
+OK, ERR_ARG, ERR_SHAPE, ERR_CAPACITY, ERR_NONFINITE, ERR_FORMAT, ERR_HIP, ERR_BUDGET, ERR_TIMEOUT, ERR_SCRATCH = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+NOALLOC_MAX_BLOCKS = 1 << 20
 
 
 class cz_params(ctypes.Structure):
@@ -58,6 +59,8 @@ def lib() -> ctypes.CDLL:
         L.cz_compress_bound.restype = sz
         L.cz_compress.argtypes = [vp, P, vp, vp, sz, vp, ctypes.POINTER(sz), vp]
         L.cz_compress.restype = i32
+        L.cz_compress_noalloc.argtypes = [vp, P, vp, vp, sz, vp, ctypes.POINTER(sz), vp]
+        L.cz_compress_noalloc.restype = i32
         L.cz_compress_strided.argtypes = [vp, P, vp, ctypes.c_uint32, ctypes.c_uint32, vp, sz, vp,
                                           ctypes.POINTER(sz), vp]
         L.cz_compress_strided.restype = i32
@@ -177,6 +180,16 @@ class Context:
                                ctypes.byref(nbytes) if sync else None, stream)
         if rc != OK:
             raise CzError(rc, "cz_compress", f"(required {nbytes.value} bytes)" if rc == ERR_CAPACITY else "")
+        return nbytes.value if sync else None
+
+    def compress_noalloc(self, p: cz_params, d_field: int, d_out: int, out_cap: int, stream: int = 0,
+                         d_out_bytes: int | None = None, sync: bool = True) -> int | None:
+        """cz_compress_noalloc; returns the stream size when sync."""
+        nbytes = ctypes.c_size_t(0)
+        rc = lib().cz_compress_noalloc(self.handle, ctypes.byref(p), d_field, d_out, out_cap, d_out_bytes,
+                                       ctypes.byref(nbytes) if sync else None, stream)
+        if rc != OK:
+            raise CzError(rc, "cz_compress_noalloc", f"(required {nbytes.value} bytes)" if rc == ERR_CAPACITY else "")
         return nbytes.value if sync else None
 
     def compress_strided(self, p: cz_params, d_state: int, ncomp: int, comp: int, d_out: int, out_cap: int,

@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -18,6 +19,44 @@
 #include "cz_host.h"
 
 using namespace czh;
+
+// Fixed device scratch of cz_compress_noalloc: the call's (ticket, status,
+// size) words, its one-field descriptor table and one look-back flag per
+// block.  Host code never passes `scratch` itself (on the host it is only a
+// stand-in for the symbol): it passes the device address that
+// hipGetSymbolAddress returned for the current device.
+namespace {
+constexpr size_t NA_WORK = 0;      // czk::CzWork
+constexpr size_t NA_DESC = 256;    // czk::FieldDesc
+constexpr size_t NA_FLAGS = 1024;  // CZ_NOALLOC_MAX_BLOCKS x u64
+constexpr size_t NA_BYTES = NA_FLAGS + (size_t)CZ_NOALLOC_MAX_BLOCKS * sizeof(uint64_t);
+static_assert(sizeof(czk::CzWork) <= NA_DESC - NA_WORK, "work words overlap the descriptor");
+static_assert(sizeof(czk::FieldDesc) <= NA_FLAGS - NA_DESC, "descriptor overlaps the flags");
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mutex;
+void *na_ptr[NA_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[NA_BYTES];
+
+namespace {
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (the caller holds a DeviceGuard for it).
+int noalloc_scratch(int device, void **out)
+{
+    std::lock_guard<std::mutex> lock(na_mutex);
+    if (device < 0 || device >= NA_MAX_DEVICES)
+        return CZ_ERR_HIP;
+    if (!na_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return CZ_ERR_HIP;
+        na_ptr[device] = p;
+    }
+    *out = na_ptr[device];
+    return CZ_OK;
+}
+}  // namespace
 
 struct cz_plan {
     cz_ctx *ctx = nullptr;
@@ -367,7 +406,8 @@ int cz_create(cz_ctx **out, int device)
                     hipMemset(ctx->work, 0, sizeof(czk::CzWork)) == hipSuccess &&
                     hipHostMalloc(&ctx->pinned, sizeof(czk::CzWork), hipHostMallocDefault) == hipSuccess &&
                     ctx->flags.ensure(4096 * sizeof(uint64_t)) == CZ_OK && ctx->batch.init() == CZ_OK &&
-                    ctx->sel.init() == CZ_OK && ctx->huff_stage.init() == CZ_OK;
+                    ctx->sel.init() == CZ_OK && ctx->huff_stage.init() == CZ_OK &&
+                    noalloc_scratch(device, &ctx->noalloc) == CZ_OK;
     if (!ok) {
         cz_destroy(ctx);
         return CZ_ERR_HIP;
@@ -488,6 +528,71 @@ int cz_compress(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_ou
                 uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream)
 {
     return compress_impl(ctx, p, d_field, 1, d_out, out_cap, d_out_bytes, h_out_bytes, stream);
+}
+
+int cz_compress_noalloc(cz_ctx *ctx, const cz_params *p, const void *d_field, void *d_out, size_t out_cap,
+                        uint64_t *d_out_bytes, size_t *h_out_bytes, void *stream)
+{
+    if (!ctx)
+        return CZ_ERR_ARG;
+    uint64_t nb = 0;
+    int rc = check_params(p, &nb);
+    if (rc != CZ_OK)
+        return rc;
+    // 64^3 blocks need a 1-2 MiB slot per resident workgroup: not in the fixed array
+    if (p->block > 32 || nb > CZ_NOALLOC_MAX_BLOCKS)
+        return CZ_ERR_SCRATCH;
+    const uint64_t bound = bound_of(*p, nb);
+    if (out_cap < bound) {
+        if (h_out_bytes)
+            *h_out_bytes = (size_t)bound;
+        return CZ_ERR_CAPACITY;
+    }
+    if (!d_out || (nb && !d_field))
+        return CZ_ERR_ARG;
+    if (!ctx->noalloc)
+        return CZ_ERR_HIP;
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t *base = static_cast<uint8_t *>(ctx->noalloc);
+    czk::CzWork *w = reinterpret_cast<czk::CzWork *>(base + NA_WORK);
+    czk::FieldDesc *desc = reinterpret_cast<czk::FieldDesc *>(base + NA_DESC);
+
+    // the prep kernel zeroes the ticket, the status and this field's flags and
+    // publishes the descriptor; the block kernels take the array's addresses
+    czk::Queue q{};
+    q.nfields = 1;
+    q.ticket = &w->ticket;
+    q.status = &w->status;
+    q.ntickets = nb;
+    q.fields = q.publish = desc;
+    q.one = describe(*p, nb, true);
+    q.one.src = d_field;
+    q.one.cstride = 1;
+    q.one.dst = d_out;
+    q.one.flags = reinterpret_cast<uint64_t *>(base + NA_FLAGS);
+    q.one.total = &w->total;
+    if (czk::launch_prep(q, true, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    if (nb) {
+        const czk::KernelKey key = key_of(ctx, *p);
+        if (czk::launch_fwd(key, q, grid_for(ctx, key, false, nb), st) != hipSuccess)
+            return CZ_ERR_HIP;
+    }
+    if (d_out_bytes &&
+        hipMemcpyAsync(d_out_bytes, &w->total, sizeof(uint64_t), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    if (h_out_bytes) {
+        if (hipMemcpyAsync(ctx->pinned, w, sizeof(czk::CzWork), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return CZ_ERR_HIP;
+        *h_out_bytes = (size_t)ctx->pinned->total;
+        return status_to_error(ctx->pinned->status);
+    }
+    // asynchronous: this call's device error joins the context's status word
+    if (czk::launch_fold_status(&w->ticket, 1, &ctx->work->status, st) != hipSuccess)
+        return CZ_ERR_HIP;
+    return CZ_OK;
 }
 
 int cz_compress_strided(cz_ctx *ctx, const cz_params *p, const void *d_state, uint32_t ncomp, uint32_t comp,
@@ -620,6 +725,7 @@ const char *cz_strerror(int code)
     case CZ_ERR_HIP: return "HIP runtime error";
     case CZ_ERR_BUDGET: return "request exceeds the memory budget";
     case CZ_ERR_TIMEOUT: return "device-side wait exceeded its bound";
+    case CZ_ERR_SCRATCH: return "field exceeds the fixed scratch of the non-allocating compress (N > 32 or too many blocks)";
     default: return "unknown error";
     }
 }

@@ -256,6 +256,7 @@ struct cz_ctx {
     czh::Staging sel;                    // selected-block decoding: (record, output block) pairs
     czh::DevBuf huff;                    // lossless stage: histogram, code table, chunk sizes
     czh::Staging huff_stage;             // lossless stage: header and code / decode tables
+    void *noalloc = nullptr;             // device address of this device's cz_compress_noalloc scratch
 };
 
 #endif  // CZ_HOST_H
