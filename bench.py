@@ -94,8 +94,25 @@ def copy_bandwidth(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
     return 2 * nbytes / t / 1e9
 
 
-def cpu_baseline(items, blocks_per_field: int):
-    """The oracle (single thread) on blocks [0, k) of every field."""
+def host_identity() -> dict:
+    """The host the CPU baseline ran on: logical CPUs and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(items, blocks_per_field: int, threads: int = 1):
+    """The oracle on blocks [0, k) of every field: one thread on k =
+    blocks_per_field, or the OpenMP timing build (parallel-for over chunks of
+    blocks, the paper's node layer) on `threads` threads and k =
+    threads x blocks_per_field, so both legs take about the same time."""
     import numpy as np
 
     import oracle
@@ -103,23 +120,53 @@ def cpu_baseline(items, blocks_per_field: int):
     oracle.build(force=False)
     t_fwd = t_inv = 0.0
     raw = 0
+    want = blocks_per_field * max(threads, 1)
+    used = want
     for lab, t, scheme, N, eps in items:
         nz, ny, nx = t.shape
         per_layer = (nx // N) * (ny // N)
-        layers = -(-blocks_per_field // per_layer)
+        layers = min(-(-want // per_layer), nz // N)
         sub = t[:layers * N].cpu().numpy()
-        k = min(blocks_per_field, per_layer * layers)
-        t0 = time.perf_counter()
-        recs, sizes = oracle.compress_blocks(sub, N, scheme, eps, 0, k)
-        t1 = time.perf_counter()
+        k = min(want, per_layer * layers)
         back = np.zeros_like(sub)
-        oracle.decompress_blocks(recs, sizes, sub.shape, N, scheme, 0, k, back)
+        t0 = time.perf_counter()
+        if threads > 1:
+            recs, sizes = oracle.compress_blocks_par(sub, N, scheme, eps, 0, k, threads)
+        else:
+            recs, sizes = oracle.compress_blocks(sub, N, scheme, eps, 0, k)
+        t1 = time.perf_counter()
+        if threads > 1:
+            oracle.decompress_blocks_par(recs, sizes, sub.shape, N, scheme, 0, k, back, threads)
+        else:
+            oracle.decompress_blocks(recs, sizes, sub.shape, N, scheme, 0, k, back)
         t2 = time.perf_counter()
         t_fwd += t1 - t0
         t_inv += t2 - t1
         raw += k * N ** 3 * sub.dtype.itemsize
-        log(f"cpu oracle {lab}: {k} blocks fwd {t1 - t0:.2f}s inv {t2 - t1:.2f}s")
-    return raw, t_fwd, t_inv
+        used = min(used, k)
+        log(f"cpu oracle {lab} ({threads} thread{'s' if threads > 1 else ''}): {k} blocks "
+            f"fwd {t1 - t0:.2f}s inv {t2 - t1:.2f}s")
+        del sub, back, recs
+    return raw, t_fwd, t_inv, used
+
+
+def cpu_baseline_line(items, blocks_per_field: int) -> dict:
+    """cpu_baseline of the bench line: all host cores (value) beside one
+    thread, forward + inverse, with the host's identity."""
+    import oracle
+
+    threads = max(1, min(oracle.par_max_threads(), os.cpu_count() or 1))
+    sraw, sf, si, sk = cpu_baseline(items, blocks_per_field, 1)
+    praw, pf, pi, pk = cpu_baseline(items, blocks_per_field, threads)
+    nf = len(items)
+    return {"value": round(praw / (pf + pi) / 1e9, 5), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"blocks [0, {pk}) of each field ({nf * pk} blocks), forward + inverse, OpenMP "
+                      f"parallel-for over chunks of 4 blocks on {threads} threads",
+            "fwd_GBps": round(praw / pf / 1e9, 5), "inv_GBps": round(praw / pi / 1e9, 5),
+            "single_thread": {"value": round(sraw / (sf + si) / 1e9, 5), "cores": 1,
+                              "sample": f"blocks [0, {sk}) of each field ({nf * sk} blocks)",
+                              "fwd_GBps": round(sraw / sf / 1e9, 5), "inv_GBps": round(sraw / si / 1e9, 5)},
+            "host": host_identity()}
 
 
 def zlib_ratio(stream_dev, nbytes: int, raw: int) -> float:
@@ -659,12 +706,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, one thread)")
-        craw, cf, ci = cpu_baseline(items, args.cpu_blocks)
-        cpu = {"value": round(craw / (cf + ci) / 1e9, 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"blocks [0, {args.cpu_blocks}) of each field ({len(items) * args.cpu_blocks} blocks), "
-                         f"forward + inverse, single-threaded",
-               "fwd_GBps": round(craw / cf / 1e9, 5), "inv_GBps": round(craw / ci / 1e9, 5)}
+        log("cpu baseline (oracle: one thread, then all host cores)")
+        cpu = cpu_baseline_line(items, args.cpu_blocks)
 
     sweep = None
     if not args.no_zlib and args.workload == "c3":

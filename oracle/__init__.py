@@ -21,6 +21,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libczoracle.so")
 SOURCES = [os.path.join(HERE, "cz_oracle.c")]
 DEPS = SOURCES + [os.path.join(HERE, "cz_oracle_t.h")]
+# Timing build for the benchmark's all-cores CPU baseline: the same oracle
+# routines under an OpenMP parallel-for over blocks (cz_oracle_omp.c).
+PAR_LIB_PATH = os.path.join(HERE, "libczoracle_omp.so")
+PAR_SOURCES = SOURCES + [os.path.join(HERE, "cz_oracle_omp.c")]
 
 # gcc flags: IEEE arithmetic exactly as written (no contraction into FMA, no
 # fast-math reassociation, no flush-to-zero).
@@ -47,6 +51,9 @@ def build(force: bool = True) -> str:
     tmp = LIB_PATH + ".tmp"
     subprocess.run(["gcc", *CFLAGS, *SOURCES, "-o", tmp, "-lm"], check=True)
     os.replace(tmp, LIB_PATH)
+    tmp = PAR_LIB_PATH + ".tmp"
+    subprocess.run(["gcc", *CFLAGS, "-fopenmp", *PAR_SOURCES, "-o", tmp, "-lm"], check=True)
+    os.replace(tmp, PAR_LIB_PATH)
     return LIB_PATH
 
 
@@ -211,6 +218,60 @@ def decompress_blocks(recs: np.ndarray, sizes: np.ndarray, shape, block: int, sc
         nx, ny, nz, block, _scheme(scheme), _ptr(recs), _ptr(sizes), b0, b1, _ptr(out))
     if rc != OK:
         raise OracleError(rc, "decompress_blocks")
+    return out
+
+
+_par = None
+
+
+def par_lib() -> ctypes.CDLL:
+    """The OpenMP timing build (built by build())."""
+    global _par
+    if _par is None:
+        if not os.path.exists(PAR_LIB_PATH):
+            build()
+        L = ctypes.CDLL(PAR_LIB_PATH)
+        vp, u32, u64, i32, f64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_double
+        L.czo_par_max_threads.argtypes = []
+        L.czo_par_max_threads.restype = i32
+        for s in ("f32", "f64"):
+            f = getattr(L, f"czo_compress_blocks_par_{s}")
+            f.argtypes = [u32, u32, u32, i32, i32, f64, vp, u64, u64, vp, vp, i32]
+            f.restype = i32
+            f = getattr(L, f"czo_decompress_blocks_par_{s}")
+            f.argtypes = [u32, u32, u32, i32, i32, vp, vp, u64, u64, vp, i32]
+            f.restype = i32
+        _par = L
+    return _par
+
+
+def par_max_threads() -> int:
+    """Threads an OpenMP region takes by default (OMP_NUM_THREADS, else the cores)."""
+    return int(par_lib().czo_par_max_threads())
+
+
+def compress_blocks_par(field: np.ndarray, block: int, scheme, epsilon: float, b0: int, b1: int, threads: int):
+    """compress_blocks on `threads` OpenMP threads (chunks of blocks per
+    thread); the same records and sizes."""
+    f = np.ascontiguousarray(field)
+    nz, ny, nx = f.shape
+    rb = record_bound(block, f.dtype.itemsize)
+    recs = np.zeros((b1 - b0) * rb, dtype=np.uint8)
+    sizes = np.zeros(b1 - b0, dtype=np.uint64)
+    rc = getattr(par_lib(), f"czo_compress_blocks_par_{_sfx(f.dtype)}")(
+        nx, ny, nz, block, _scheme(scheme), float(epsilon), _ptr(f), b0, b1, _ptr(recs), _ptr(sizes), threads)
+    if rc != OK:
+        raise OracleError(rc, "compress_blocks_par")
+    return recs, sizes
+
+
+def decompress_blocks_par(recs: np.ndarray, sizes: np.ndarray, shape, block: int, scheme, b0: int, b1: int,
+                          out: np.ndarray, threads: int) -> np.ndarray:
+    nz, ny, nx = shape
+    rc = getattr(par_lib(), f"czo_decompress_blocks_par_{_sfx(out.dtype)}")(
+        nx, ny, nz, block, _scheme(scheme), _ptr(recs), _ptr(sizes), b0, b1, _ptr(out), threads)
+    if rc != OK:
+        raise OracleError(rc, "decompress_blocks_par")
     return out
 
 

@@ -102,3 +102,24 @@ def test_block_range_errors(oracle):
     with pytest.raises(oracle.OracleError) as e:
         oracle.decompress_blocks(bad, sizes, f.shape, 8, "W4", 0, 2, out)
     assert e.value.code == oracle.ERR_FORMAT
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("N,shape", CASES)
+def test_openmp_timing_build_equals_one_thread(oracle, N, shape, dt):
+    """The all-cores timing build (OpenMP parallel-for over chunks of blocks,
+    the node layer of Sec. 2.1) yields the records, sizes and decoded blocks
+    of the single-threaded block-range call, for any thread count."""
+    f = field_of(shape, dt, 303 + N)
+    eps = 1e-2 * float(f.max() - f.min())
+    nb = (shape[0] // N) * (shape[1] // N) * (shape[2] // N)
+    b0, b1 = 1, nb
+    recs, sizes = oracle.compress_blocks(f, N, "W4_li", eps, b0, b1)
+    want = np.zeros_like(f)
+    oracle.decompress_blocks(recs, sizes, f.shape, N, "W4_li", b0, b1, want)
+    for threads in (1, 3, 8):
+        pr, ps = oracle.compress_blocks_par(f, N, "W4_li", eps, b0, b1, threads)
+        assert np.array_equal(ps, sizes) and np.array_equal(pr, recs), threads
+        got = np.zeros_like(f)
+        oracle.decompress_blocks_par(pr, ps, f.shape, N, "W4_li", b0, b1, got, threads)
+        assert got.tobytes() == want.tobytes(), threads
