@@ -229,6 +229,13 @@ int grid_for(const cz_ctx *ctx, const czk::KernelKey &key, bool inverse, uint64_
     return (int)(g ? g : 1);
 }
 
+// Forward tickets of a field of nb blocks (small blocks go in groups).
+uint64_t fwd_tickets(const czk::KernelKey &key, uint64_t nb)
+{
+    const uint64_t g = czk::fwd_blocks_per_ticket(key);
+    return (nb + g - 1) / g;
+}
+
 size_t scratch_need(const czk::KernelKey &key, int grid)
 {
     return key.block == 64 ? (size_t)grid * 64 * 64 * 64 * key.elem_bytes : 0;
@@ -263,7 +270,7 @@ int layout_batch(const cz_ctx *ctx, bool forward, int n, const cz_params *ps, La
             L->order.push_back(i);
             L->flag_base[i] = L->flags_total;
             L->flags_total += std::max<uint64_t>(L->nblocks[i], 1);
-            t += L->nblocks[i];
+            t += forward ? fwd_tickets(key, L->nblocks[i]) : L->nblocks[i];
         }
         L->tickets.push_back(t);
         const int g = grid_for(ctx, key, !forward, t);
@@ -302,7 +309,7 @@ void stage_batch(BatchWork &w, const Layout &L, const cz_params *ps, const void 
             d.src = srcs[i];
             d.dst = dsts[i];
             d.first = t;
-            t += L.nblocks[i];
+            t += L.forward ? fwd_tickets(L.keys[c], L.nblocks[i]) : L.nblocks[i];
             if (L.forward) {
                 d.flags = flags + L.flag_base[i];
                 d.total = totals + i;
@@ -492,8 +499,9 @@ static int compress_impl(cz_ctx *ctx, const cz_params *p, const void *d_field, u
     if ((rc = ctx->flags.ensure(std::max<uint64_t>(nb, 1) * sizeof(uint64_t))) != CZ_OK)
         return rc;
 
+    const czk::KernelKey key = key_of(ctx, *p);
     czk::Queue q = work_queue(ctx);
-    q.ntickets = nb;
+    q.ntickets = fwd_tickets(key, nb);
     q.fields = q.publish = ctx->one;
     q.one = describe(*p, nb, true);
     q.one.src = d_field;
@@ -504,8 +512,7 @@ static int compress_impl(cz_ctx *ctx, const cz_params *p, const void *d_field, u
     if (czk::launch_prep(q, true, st) != hipSuccess)
         return CZ_ERR_HIP;
     if (nb) {
-        const czk::KernelKey key = key_of(ctx, *p);
-        const int grid = grid_for(ctx, key, false, nb);
+        const int grid = grid_for(ctx, key, false, q.ntickets);
         if ((rc = ctx->scratch.ensure(scratch_need(key, grid))) != CZ_OK)
             return rc;
         q.scratch = ctx->scratch.ptr;
@@ -560,11 +567,12 @@ int cz_compress_noalloc(cz_ctx *ctx, const cz_params *p, const void *d_field, vo
 
     // the prep kernel zeroes the ticket, the status and this field's flags and
     // publishes the descriptor; the block kernels take the array's addresses
+    const czk::KernelKey key = key_of(ctx, *p);
     czk::Queue q{};
     q.nfields = 1;
     q.ticket = &w->ticket;
     q.status = &w->status;
-    q.ntickets = nb;
+    q.ntickets = fwd_tickets(key, nb);
     q.fields = q.publish = desc;
     q.one = describe(*p, nb, true);
     q.one.src = d_field;
@@ -574,11 +582,8 @@ int cz_compress_noalloc(cz_ctx *ctx, const cz_params *p, const void *d_field, vo
     q.one.total = &w->total;
     if (czk::launch_prep(q, true, st) != hipSuccess)
         return CZ_ERR_HIP;
-    if (nb) {
-        const czk::KernelKey key = key_of(ctx, *p);
-        if (czk::launch_fwd(key, q, grid_for(ctx, key, false, nb), st) != hipSuccess)
-            return CZ_ERR_HIP;
-    }
+    if (nb && czk::launch_fwd(key, q, grid_for(ctx, key, false, q.ntickets), st) != hipSuccess)
+        return CZ_ERR_HIP;
     if (d_out_bytes &&
         hipMemcpyAsync(d_out_bytes, &w->total, sizeof(uint64_t), hipMemcpyDeviceToDevice, st) != hipSuccess)
         return CZ_ERR_HIP;

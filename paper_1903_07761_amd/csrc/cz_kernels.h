@@ -77,8 +77,12 @@ hipError_t launch_prep(const Queue &q, bool forward, hipStream_t st);
 hipError_t launch_fold_status(const uint32_t *counters, int nclass, uint32_t *status, hipStream_t st);
 // Resident workgroups per CU of the (fwd or inv) kernel for key.
 int occupancy(const KernelKey &key, bool inverse);
-// Forward launches one workgroup per block up to 32^3 (grid = tickets).
+// Forward launches one workgroup per ticket up to 32^3 (grid = tickets).
 bool fwd_one_block_per_workgroup(const KernelKey &key);
+// Blocks a forward ticket covers: a group of consecutive blocks of one field
+// for 8^3 and 16^3 (one per wavefront), else one.  A field of nb blocks owns
+// ceil(nb / this) forward tickets, and its look-back flags are per ticket.
+uint32_t fwd_blocks_per_ticket(const KernelKey &key);
 // Number of compiled shape variants for (block, elem_bytes).
 int variant_count(uint32_t block, uint32_t elem_bytes);
 // Upper bound on the workgroups of a launch (0: none).

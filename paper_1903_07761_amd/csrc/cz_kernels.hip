@@ -57,6 +57,16 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Orders LDS accesses among the lanes of one wavefront (a wavefront's LDS
+// instructions execute in program order; the fences keep the compiler from
+// moving one lane's access across another lane's).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // Exclusive scan of one u32 per thread over a workgroup of NT threads.
 // s_w must hold NT/64 + 1 words; the total lands in s_w[NT/64].
 template <int NT>
@@ -625,6 +635,274 @@ __global__ __launch_bounds__(N *N / R, (FwdWaves<T, N, Z, R, ZP>::value)) void f
                 const int wi = G::word(z, r, wave);
                 const T v = park[(z - ZP) * G::PS + (yq + r * G::YR) * G::PX + x];
                 buf_store(v, vr, (s_pre[wi] + mbcnt(s_words[wi])) * (uint32_t)sizeof(T));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------- forward, small blocks
+
+// Blocks of 8^3 and 16^3 transform in well under a microsecond each; with one
+// block per workgroup the single ticket counter (one atomic per block, which
+// the L2 serialises) and the per-block look-back set the pace.  Here a
+// workgroup takes one ticket for a group of SG consecutive blocks and runs
+// them side by side, one block per wavefront: each wavefront holds its
+// block's z-columns in VGPRs (lane (x, yq) owns columns y = yq + r N/R),
+// transforms its x- and y-lines through its own LDS region by slab groups of
+// SZ planes (one line per lane per pass), decimates with one ballot per mask
+// word, and scans its word counts with cross-lane shuffles.  The group then
+// publishes one size and runs one look-back over group-indexed flags; each
+// record lands at the group's offset plus the sizes of the group's earlier
+// blocks, the exclusive scan of Sec. 2.2 taken in two levels.
+template <typename T, int N>
+struct SmallGeom {
+    static constexpr int R = N * N / 64;        // columns per lane: 1 (8^3), 4 (16^3)
+    static constexpr int YR = N / R;            // row stride between a lane's columns
+    static constexpr int SZ = 64 / N;           // planes per slab group: a pass is 64 lines
+    static constexpr int PX = N + 1;            // staging row pitch (odd)
+    static constexpr int PS = N * PX;           // staging slab pitch
+    static constexpr int REGION = SZ * PS;      // LDS elements per wavefront
+    static constexpr int WORDS = N * R;         // mask words per block (= N^3 / 64)
+    static constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
+    static_assert(N == 8 || N == 16, "one block per wavefront: 8^3 or 16^3");
+    static_assert(WORDS <= 64, "one mask word per lane at most");
+    // the coarse level of a 16^3 block (8^3, pitches 9 and 72) reuses the region
+    static_assert(N == 8 || REGION >= 8 * 72, "coarse cube fits the region");
+};
+
+// Blocks per workgroup (= wavefronts): 16 for 8^3; 8 for float and 4 for
+// double 16^3 (measured on 512^3 fields: 8 float / 4 double 16^3 blocks a
+// group beat 16 and 4 / 8, and 16 8^3 blocks beat 8).
+template <typename T, int N>
+struct SmallGroup {
+    static constexpr int value = N == 8 ? 16 : sizeof(T) == 8 ? 4 : 8;
+};
+
+// Every line along AXIS of the n^3 cube at the start of an LDS region with
+// pitches (1, PY, PZ): n*n lines, one per lane for the first n*n lanes.
+template <typename T, int S, int n, int AXIS, int PY, int PZ>
+__device__ __forceinline__ void wave_lines(T *reg, int lane)
+{
+    if (lane < n * n) {
+        const int i = lane % n, j = lane / n;
+        int base, stride;
+        if constexpr (AXIS == 0) {
+            base = i * PY + j * PZ;
+            stride = 1;
+        } else if constexpr (AXIS == 1) {
+            base = i + j * PZ;
+            stride = PY;
+        } else {
+            base = i + j * PY;
+            stride = PZ;
+        }
+        T v[n];
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            v[k] = reg[base + k * stride];
+        line_fwd<T, S, n>(v);
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            reg[base + k * stride] = v[k];
+    }
+}
+
+// The 64 lines along x (AXIS 0) or y (AXIS 1) of SZ = 64 / N staged planes
+// (pitches 1, PX, PS), one per lane: lane = i + N j, i the other in-plane
+// coordinate, j the plane.
+template <typename T, int S, int N, int AXIS, int PX, int PS>
+__device__ __forceinline__ void slab_lines(T *reg, int lane)
+{
+    const int i = lane % N, j = lane / N;
+    const int base = j * PS + (AXIS == 0 ? i * PX : i);
+    constexpr int stride = AXIS == 0 ? 1 : PX;
+    T v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        v[k] = reg[base + k * stride];
+    line_fwd<T, S, N>(v);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        reg[base + k * stride] = v[k];
+}
+
+template <typename T, int N, int S>
+__global__ __launch_bounds__((64 * SmallGroup<T, N>::value)) void fwd_small_kernel(Queue q)
+{
+    using G = SmallGeom<T, N>;
+    constexpr int SG = SmallGroup<T, N>::value;
+    constexpr int R = G::R;
+    __shared__ T lds[SG * G::REGION];
+    __shared__ uint64_t s_ticket;
+    __shared__ uint32_t s_field;
+    __shared__ uint64_t s_size[SG];
+    __shared__ uint64_t s_goff;
+
+    const int tid = threadIdx.x;
+    const int lane = (int)lane_id();
+    const int w = tid / 64;  // this wavefront's block within the group
+    const int x = lane % N, yq = lane / N;
+    T *reg = lds + w * G::REGION;
+
+    if (tid == 0) {
+        const uint64_t t = atomicAdd(q.ticket, 1u);
+        s_ticket = t;
+        s_field = t < q.ntickets ? field_of_ticket(q, t) : 0u;
+    }
+    lds_barrier();
+    const uint64_t t = uniform64(s_ticket);
+    if (t >= q.ntickets)
+        return;
+    const FieldView a = field_view(q, s_field);
+    const uint64_t g = t - a.first;  // the group within the field
+    const uint64_t b = g * SG + (uint64_t)w;
+    const bool live = b < a.nblocks;  // the field's last group may be short
+
+    T c[R][N];
+    if (live) {
+        const uint32_t lane_off = ((uint32_t)yq * a.nx + (uint32_t)x) * a.cs;
+        load_planes<T, N, N, R>(a, b, 0, lane_off, c);
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int z = 0; z < N; ++z)
+                c[r][z] = T(0);
+    }
+
+    // finest level: x- and y-lines by slab groups of SZ planes, z in VGPRs
+#pragma unroll
+    for (int sg = 0; sg < N / G::SZ; ++sg) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int j = 0; j < G::SZ; ++j)
+                reg[j * G::PS + (yq + r * G::YR) * G::PX + x] = c[r][sg * G::SZ + j];
+        wave_lds_sync();
+        slab_lines<T, S, N, 0, G::PX, G::PS>(reg, lane);  // x-lines of the SZ planes
+        wave_lds_sync();
+        slab_lines<T, S, N, 1, G::PX, G::PS>(reg, lane);  // y-lines
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int j = 0; j < G::SZ; ++j)
+                c[r][sg * G::SZ + j] = reg[j * G::PS + (yq + r * G::YR) * G::PX + x];
+        wave_lds_sync();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        line_fwd<T, S, N>(c[r]);
+
+    // 16^3: the level at n = 8 on the coarse cube, every pass in LDS
+    if constexpr (N == 16) {
+        constexpr int QX = 9, QS = 72;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int y = yq + r * G::YR;
+            if (x < 8) {
+#pragma unroll
+                for (int z = 0; z < 8; ++z)
+                    reg[z * QS + y * QX + x] = c[r][z];
+            }
+        }
+        wave_lds_sync();
+        wave_lines<T, S, 8, 0, QX, QS>(reg, lane);
+        wave_lds_sync();
+        wave_lines<T, S, 8, 1, QX, QS>(reg, lane);
+        wave_lds_sync();
+        wave_lines<T, S, 8, 2, QX, QS>(reg, lane);
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int y = yq + r * G::YR;
+            if (x < 8) {
+#pragma unroll
+                for (int z = 0; z < 8; ++z)
+                    c[r][z] = reg[z * QS + y * QX + x];
+            }
+        }
+    }
+
+    // decimation: the 4^3 corner and |c| >= eps; word (z, r) is the ballot of
+    // 64 consecutive q, kept by lane z R + r
+    bool bad = false;
+    uint64_t myword = 0;
+#pragma unroll
+    for (int z = 0; z < N; ++z) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = yq + r * G::YR;
+            const T v = c[r][z];
+            bad |= !finite(v);
+            const bool keep = (z < 4 && x < 4 && y < 4) || keep_test<T>(v, a);
+            const uint64_t m = __ballot(keep);
+            myword = lane == z * R + r ? m : myword;
+        }
+    }
+    if (live && bad)
+        report(q, s_field, STATUS_NONFINITE);
+    const uint32_t cnt = lane < G::WORDS ? (uint32_t)__popcll(myword) : 0u;
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off, 64);
+        if (lane >= off)
+            inc += o;
+    }
+    const uint32_t pre = inc - cnt;  // kept values before word `lane`
+    const uint32_t nnz = __builtin_amdgcn_readlane(inc, 63);
+    const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
+    const uint64_t rbytes = live ? (used + 15ull) & ~15ull : 0ull;
+
+    // one size and one look-back for the group
+    if (lane == 0)
+        s_size[w] = rbytes;
+    lds_barrier();
+    if (w == 0) {
+        uint64_t total = 0;
+#pragma unroll
+        for (int k = 0; k < SG; ++k)
+            total += s_size[k];
+        const uint64_t o = lookback_wave(a.flags, g, total, q.status, q.fstatus ? q.fstatus + s_field : nullptr);
+        if (lane == 0)
+            s_goff = o;
+    }
+    lds_barrier();
+    if (!live)
+        return;
+    uint64_t off = s_goff;
+    for (int k = 0; k < w; ++k)
+        off += s_size[k];
+
+    uint8_t *out = static_cast<uint8_t *>(a.dst);
+    uint8_t *rec = out + a.p0 + off;
+    if (lane == 0) {
+        reinterpret_cast<uint32_t *>(rec)[0] = nnz;
+        reinterpret_cast<uint32_t *>(rec)[1] = 0u;
+        reinterpret_cast<uint64_t *>(out + 64)[b + 1] = off + rbytes;
+        for (uint64_t p = used; p < rbytes; p += 4)
+            *reinterpret_cast<uint32_t *>(rec + p) = 0u;
+        if (b + 1 == a.nblocks) {
+            *reinterpret_cast<uint64_t *>(out + 56) = off + rbytes;
+            if (a.total)
+                *a.total = a.p0 + off + rbytes;
+        }
+    }
+    if (lane < G::WORDS)
+        reinterpret_cast<uint64_t *>(rec + 8)[lane] = myword;
+    const rsrc_t vr = make_rsrc(rec + 8 + G::MASK_BYTES, nnz * (uint32_t)sizeof(T));
+#pragma unroll
+    for (int z = 0; z < N; ++z) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int wi = z * R + r;
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)myword, wi);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(myword >> 32), wi);
+            const uint64_t word = ((uint64_t)hi << 32) | lo;
+            if ((word >> lane) & 1u) {
+                const uint32_t rank = __builtin_amdgcn_readlane(pre, wi) + mbcnt(word);
+                buf_store(c[r][z], vr, rank * (uint32_t)sizeof(T));
             }
         }
     }
@@ -1308,9 +1586,13 @@ static int occupancy_t(bool inverse)
 {
     using P = Shape<T, N, V>;
     int nb = 0;
-    hipError_t e =
-        inverse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, inv_kernel<T, N, S, P::Z, P::R>, P::NT, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<T, N, S, P::Z, P::R, P::ZP>, P::NT, 0);
+    hipError_t e;
+    if constexpr (N == 32)
+        e = inverse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, inv_kernel<T, N, S, P::Z, P::R>, P::NT, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<T, N, S, P::Z, P::R, P::ZP>,
+                                                                   P::NT, 0);
+    else  // smaller blocks: only the inverse uses this tiling
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, inv_kernel<T, N, S, P::Z, P::R>, P::NT, 0);
     return e == hipSuccess ? nb : 0;
 }
 
@@ -1358,8 +1640,35 @@ static hipError_t scratch_dispatch(bool inverse, const Queue &q, int grid, hipSt
     default: CZ_VARIANTS(T, 32, OP, ARGS)                                                                    \
     }
 
+template <typename T, int N, int S>
+static hipError_t launch_fwd_small_t(const Queue &q, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((fwd_small_kernel<T, N, S>), dim3(grid), dim3(64 * SmallGroup<T, N>::value), 0, st, q);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_fwd_small(const KernelKey &key, const Queue &q, int grid, hipStream_t st)
+{
+    if (key.block == 8) {
+        switch (key.scheme) {
+        case W4: return launch_fwd_small_t<T, 8, W4>(q, grid, st);
+        case W4LI: return launch_fwd_small_t<T, 8, W4LI>(q, grid, st);
+        default: return launch_fwd_small_t<T, 8, W3AI>(q, grid, st);
+        }
+    }
+    switch (key.scheme) {
+    case W4: return launch_fwd_small_t<T, 16, W4>(q, grid, st);
+    case W4LI: return launch_fwd_small_t<T, 16, W4LI>(q, grid, st);
+    default: return launch_fwd_small_t<T, 16, W3AI>(q, grid, st);
+    }
+}
+
 hipError_t launch_fwd(const KernelKey &key, const Queue &q, int grid, hipStream_t st)
 {
+    if (key.block <= 16)
+        return key.elem_bytes == 4 ? launch_fwd_small<float>(key, q, grid, st)
+                                   : launch_fwd_small<double>(key, q, grid, st);
     if (key.block == 64) {
         if (key.elem_bytes == 4) {
             switch (key.scheme) {
@@ -1375,9 +1684,9 @@ hipError_t launch_fwd(const KernelKey &key, const Queue &q, int grid, hipStream_
         }
     }
     if (key.elem_bytes == 4) {
-        CZ_DISPATCH(float, launch_fwd_t, (q, grid, st))
+        CZ_VARIANTS(float, 32, launch_fwd_t, (q, grid, st))
     } else {
-        CZ_DISPATCH(double, launch_fwd_t, (q, grid, st))
+        CZ_VARIANTS(double, 32, launch_fwd_t, (q, grid, st))
     }
 }
 
@@ -1404,10 +1713,36 @@ hipError_t launch_inv(const KernelKey &key, const Queue &q, int grid, hipStream_
     }
 }
 
+template <typename T, int N, int S>
+static int occupancy_small_t()
+{
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_small_kernel<T, N, S>,
+                                                                      64 * SmallGroup<T, N>::value, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
 int occupancy(const KernelKey &key, bool inverse)
 {
     if (key.block == 64)
         return 1;  // one scratch slot per workgroup, one workgroup per CU
+    if (!inverse && key.block <= 16) {
+        const bool f = key.elem_bytes == 4;
+        if (key.block == 8)
+            return key.scheme == W4 ? (f ? occupancy_small_t<float, 8, W4>() : occupancy_small_t<double, 8, W4>())
+                 : key.scheme == W4LI ? (f ? occupancy_small_t<float, 8, W4LI>() : occupancy_small_t<double, 8, W4LI>())
+                 : (f ? occupancy_small_t<float, 8, W3AI>() : occupancy_small_t<double, 8, W3AI>());
+        return key.scheme == W4 ? (f ? occupancy_small_t<float, 16, W4>() : occupancy_small_t<double, 16, W4>())
+             : key.scheme == W4LI ? (f ? occupancy_small_t<float, 16, W4LI>() : occupancy_small_t<double, 16, W4LI>())
+             : (f ? occupancy_small_t<float, 16, W3AI>() : occupancy_small_t<double, 16, W3AI>());
+    }
+    if (!inverse) {
+        if (key.elem_bytes == 4) {
+            CZ_VARIANTS(float, 32, occupancy_t, (inverse))
+        } else {
+            CZ_VARIANTS(double, 32, occupancy_t, (inverse))
+        }
+    }
     if (key.elem_bytes == 4) {
         CZ_DISPATCH(float, occupancy_t, (inverse))
     } else {
@@ -1416,6 +1751,15 @@ int occupancy(const KernelKey &key, bool inverse)
 }
 
 bool fwd_one_block_per_workgroup(const KernelKey &key) { return key.block <= 32; }
+
+uint32_t fwd_blocks_per_ticket(const KernelKey &key)
+{
+    if (key.block == 8)
+        return key.elem_bytes == 8 ? SmallGroup<double, 8>::value : SmallGroup<float, 8>::value;
+    if (key.block == 16)
+        return key.elem_bytes == 8 ? SmallGroup<double, 16>::value : SmallGroup<float, 16>::value;
+    return 1u;
+}
 
 // 64^3 variants differ only in how many workgroups (each with its scratch
 // slot) are resident at once: 256, 128 or 64.  Fewer slots keep the scratch

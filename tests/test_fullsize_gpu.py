@@ -117,3 +117,21 @@ def test_32cubed_inverse_persistent_many_blocks(oracle):
     for v in range(_cz.variant_count(32, 4)):
         codec.set_variant(32, torch.float32, "W4_li", v)
         whole_parity(codec, oracle, f, 32, "W4_li", eps, f"32^3 f32 W4_li variant {v}")
+
+
+@pytest.mark.parametrize("N,shape", [(8, (120, 200, 232)), (16, (144, 240, 208))])
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_small_blocks_many_groups(codec, oracle, N, shape, dt):
+    """8^3 and 16^3 blocks go in groups of one workgroup (one block per
+    wavefront, one ticket and one look-back per group): 10875 8^3 blocks
+    (680 groups of 16) and 1755 16^3 blocks, counts that leave the last group
+    short, so the group look-back runs many steps past its first 64
+    predecessors and each record's offset adds the sizes of the earlier
+    blocks of its group."""
+    from paper_1903_07761_amd import fields
+
+    n = max(shape)
+    f = fields.bubble_cloud(n, 1909, nbubbles=60, dtype=dt, device="cuda")[: shape[0], : shape[1], : shape[2]]
+    f = f.contiguous()
+    for scheme in ("W4", "W4_li", "W3_ai"):
+        whole_parity(codec, oracle, f, N, scheme, 1e-3 * fields.value_range(f), f"{N}^3 {dt} {scheme}")
