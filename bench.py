@@ -599,6 +599,90 @@ def main_c5(args):
         raise SystemExit("served outputs differ from the oracle")
 
 
+def main_small(args):
+    """Small blocks (Sec. 3.2 compares 8^3, 16^3 and 32^3 blocks): 512^3
+    bubble clouds (float32 and float64), W4_li and W3_ai, eps 1e-3 of range,
+    blocks of 8^3 and 16^3; forward and inverse of each configuration timed
+    with HIP events on the launch stream over `steps` repeats.  The streams
+    are checked against the oracle on a 64^3 corner of each field."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1903_07761_amd import fields as G
+    from paper_1903_07761_amd.codec import Codec
+
+    dev = torch.device("cuda", 0)
+    codec = Codec(0)
+    stream = torch.cuda.current_stream(dev)
+    oracle.build(force=False)
+    rows = []
+    raw_total = 0.0
+    t_total = 0.0
+    for dt in (torch.float32, torch.float64):
+        f = G.bubble_cloud(512, 1904, dtype=dt, device=dev)
+        eps_frac = 1e-3
+        eps = eps_frac * G.value_range(f)
+        raw = f.numel() * f.element_size()
+        corner = f[:64, :64, :64].contiguous()
+        for N in (8, 16):
+            for scheme in ("W4_li", "W3_ai"):
+                buf, n = codec.compress(corner, N, scheme, eps)
+                same = buf[:n].cpu().numpy().tobytes() == oracle.compress(corner.cpu().numpy(), N, scheme, eps)
+                out = torch.empty(codec.bound(f.shape, f.dtype, N), dtype=torch.uint8, device=dev)
+                back = torch.empty_like(f)
+                nb = torch.zeros(1, dtype=torch.int64, device=dev)
+                p = codec.params(f, N, scheme, eps)
+                for _ in range(max(args.warmup, 1)):
+                    codec.compress(f, N, scheme, eps, out=out, sync=False, out_bytes=nb)
+                    codec.decompress(out, out.numel(), out=back, expected=p)
+                torch.cuda.synchronize()
+                ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+                for s in range(args.steps):
+                    ev[s][0].record(stream)
+                    codec.compress(f, N, scheme, eps, out=out, sync=False, out_bytes=nb)
+                    ev[s][1].record(stream)
+                    codec.decompress(out, out.numel(), out=back, expected=p)
+                    ev[s][2].record(stream)
+                torch.cuda.synchronize()
+                if codec.status() != 0:
+                    raise SystemExit("device status after the small-block runs")
+                fwd = float(np.median([e[0].elapsed_time(e[1]) for e in ev]))
+                inv = float(np.median([e[1].elapsed_time(e[2]) for e in ev]))
+                sz = int(nb.item())
+                rows.append({"dtype": str(dt).split(".")[-1], "block": N, "scheme": scheme, "fwd_ms": round(fwd, 4),
+                             "inv_ms": round(inv, 4), "cr_stage1": round(raw / sz, 3),
+                             "fwd_GBps_algo": round((raw + sz) / fwd / 1e6, 1),
+                             "inv_GBps_algo": round((raw + sz) / inv / 1e6, 1),
+                             "corner_stream_equals_oracle": same})
+                log(f"small: {rows[-1]}")
+                raw_total += 2 * raw
+                t_total += (fwd + inv) / 1e3
+                del out, back
+        del f
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "GB/s raw field (FWT+threshold+pack, and inverse)",
+        "value": round(raw_total / 2 / t_total / 1e9, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": max(args.warmup, 1),
+        "ms_per_step": round(t_total * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "512^3 bubble clouds, float32 and float64, blocks 8^3 and 16^3, W4_li and W3_ai, "
+                               "eps 1e-3 of range (median of the timed repeats)"},
+        "runs": rows,
+    }
+    print(json.dumps(line), flush=True)
+    if not all(r["corner_stream_equals_oracle"] for r in rows):
+        raise SystemExit("a small-block stream differs from the oracle's")
+
+
 def main_lossless(args):
     """The GPU lossless stage alone, on the streams of two of C3's fields:
     rho (noisy: the stream is mostly kept coefficients) and u (smooth: mostly
@@ -639,7 +723,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4", "c5", "lossless"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "c4", "c5", "lossless", "small"])
     ap.add_argument("--requests", type=int, default=2000, help="c5: number of serving requests")
     ap.add_argument("--cpu-blocks", type=int, default=400, help="oracle sample: blocks per field")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -661,6 +745,8 @@ def main():
         return main_c5(args)
     if args.workload == "lossless":
         return main_lossless(args)
+    if args.workload == "small":
+        return main_small(args)
 
     from paper_1903_07761_amd import metrics
     from paper_1903_07761_amd.codec import Codec
@@ -779,6 +865,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "fields": len(items), "grid": list(items[0][1].shape), "block": items[0][3],
                    "scheme": items[0][2], "raw_bytes_per_step": raw_total},
+        "stream_bytes": sizes,
         "fwd_GBps": round(fwd_gbps, 2),
         "inv_GBps": round(inv_gbps, 2),
         "psnr_db": psnr,
