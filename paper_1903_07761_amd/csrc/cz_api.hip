@@ -431,6 +431,8 @@ void cz_destroy(cz_ctx *ctx)
     (void)hipDeviceSynchronize();
     ctx->flags.release();
     ctx->scratch.release();
+    ctx->defer.release();
+    ctx->dsizes.release();
     ctx->batch.release();
     ctx->sel.release();
     ctx->huff.release();
@@ -509,6 +511,15 @@ static int compress_impl(cz_ctx *ctx, const cz_params *p, const void *d_field, u
     q.one.dst = d_out;
     q.one.flags = static_cast<uint64_t *>(ctx->flags.ptr);
     q.one.total = &ctx->work->total;
+    // 32^3 blocks whose record fits a slot skip the look-back (fix-up below)
+    const bool defer = nb && p->block == 32;
+    if (defer) {
+        if ((rc = ctx->defer.ensure((size_t)nb * czk::DEFER_SLOT)) != CZ_OK ||
+            (rc = ctx->dsizes.ensure(czk::defer_sizes_bytes(nb))) != CZ_OK)
+            return rc;
+        q.one.defer = static_cast<uint8_t *>(ctx->defer.ptr);
+        q.one.sizes = static_cast<uint32_t *>(ctx->dsizes.ptr);
+    }
     if (czk::launch_prep(q, true, st) != hipSuccess)
         return CZ_ERR_HIP;
     if (nb) {
@@ -517,6 +528,8 @@ static int compress_impl(cz_ctx *ctx, const cz_params *p, const void *d_field, u
             return rc;
         q.scratch = ctx->scratch.ptr;
         if (czk::launch_fwd(key, q, grid, st) != hipSuccess)
+            return CZ_ERR_HIP;
+        if (defer && czk::launch_defer_fix(q, st) != hipSuccess)
             return CZ_ERR_HIP;
     }
     if (d_out_bytes &&

@@ -15,6 +15,13 @@ constexpr int SCRATCH_THREADS = 512;
 // Status bits latched by the kernels.
 enum : uint32_t { STATUS_NONFINITE = 1u, STATUS_FORMAT = 2u, STATUS_TIMEOUT = 4u };
 
+// Deferred records (32^3 forward of a single field): a block whose record
+// fits DEFER_SLOT bytes writes it to slot b of the field's defer area instead
+// of waiting for its predecessors' sizes; a fix-up launch places it.
+constexpr uint32_t DEFER_SLOT = 8192;
+constexpr uint32_t DEFER_BIT = 1u << 31;  // in sizes[b]: the record sits in its slot
+constexpr uint32_t FIX_CHUNK = 1024;      // blocks per workgroup of the fix-up
+
 // Per-context device workspace header (plain calls use its counters).
 struct CzWork {
     uint32_t ticket;  // next block ticket
@@ -41,6 +48,8 @@ struct FieldDesc {
     float eps_f;          // smallest float >= eps (the same test for float data)
     uint32_t cstride;     // forward: elements between consecutive cells of src (1 = a plain field)
     uint32_t header[16];  // forward: the 64-byte header, payload size 0
+    uint8_t *defer;       // forward, optional: nblocks slots of DEFER_SLOT bytes (32^3 blocks)
+    uint32_t *sizes;      // with defer: nblocks record sizes, then the fix-up's chunk flags (u64)
 };
 
 // A device work queue: tickets [0, ntickets) map, in order, onto the blocks
@@ -73,6 +82,12 @@ hipError_t launch_inv(const KernelKey &key, const Queue &q, int grid, hipStream_
 // Reset the queue's ticket and status; forward: clear each field's flags and
 // write its header, offset 0 and the pad before its payload.
 hipError_t launch_prep(const Queue &q, bool forward, hipStream_t st);
+// After a single-field forward with deferred records: offsets of every block
+// (chunked scan of sizes[]), deferred records moved from their slots into the
+// stream, the payload size in the header and *total.
+hipError_t launch_defer_fix(const Queue &q, hipStream_t st);
+// Bytes of the sizes area (sizes, then 8-byte-aligned chunk flags) for nblocks.
+size_t defer_sizes_bytes(uint64_t nblocks);
 // OR the status words of nclass (ticket, status) counter pairs into *status.
 hipError_t launch_fold_status(const uint32_t *counters, int nclass, uint32_t *status, hipStream_t st);
 // Resident workgroups per CU of the (fwd or inv) kernel for key.

@@ -480,6 +480,10 @@ __global__ __launch_bounds__(N *N / R, (FwdWaves<T, N, Z, R, ZP>::value)) void f
     const FieldView a = field_view(q, s_field);
     const uint64_t b = t - a.first;
     const uint32_t lane_off = ((uint32_t)yq * a.nx + (uint32_t)x) * a.cs;  // element offset of (x, yq) in a z-plane
+    // the defer area (read now, so the scalar loads overlap the block's loads)
+    ConstDesc *desc = (ConstDesc *)q.fields + __builtin_amdgcn_readfirstlane(s_field);
+    uint8_t *const slots = desc->defer;
+    uint32_t *const sizes = desc->sizes;
 
     // load: for each z and r one coalesced row segment of N elements; the
     // rows of slab group g+1 stay in flight while group g is transformed
@@ -591,26 +595,42 @@ __global__ __launch_bounds__(N *N / R, (FwdWaves<T, N, Z, R, ZP>::value)) void f
 
     const uint64_t used = 8ull + G::MASK_BYTES + (uint64_t)nnz * sizeof(T);
     const uint64_t rbytes = (used + 15ull) & ~15ull;
-    if (tid < 64) {
-        const uint64_t o = lookback_wave(a.flags, b, rbytes, q.status, q.fstatus ? q.fstatus + s_field : nullptr);
-        if (tid == 0)
-            s_off = o;
+    // a record that fits a slot of the field's defer area goes there without
+    // waiting for the predecessors' sizes (its own size is published for the
+    // blocks that do look back); the fix-up launch places it
+    const bool deferred = slots != nullptr && rbytes <= DEFER_SLOT;
+    uint64_t off = 0;
+    if (deferred) {
+        if (tid == 0) {
+            atomic_store_u64(&a.flags[b], FLAG_AGG | rbytes);
+            sizes[b] = (uint32_t)rbytes | DEFER_BIT;
+        }
+    } else {
+        if (tid < 64) {
+            const uint64_t o = lookback_wave(a.flags, b, rbytes, q.status, q.fstatus ? q.fstatus + s_field : nullptr);
+            if (tid == 0)
+                s_off = o;
+        }
+        lds_barrier();
+        off = s_off;
+        if (tid == 0 && sizes)
+            sizes[b] = (uint32_t)rbytes;
     }
-    lds_barrier();
-    const uint64_t off = s_off;
     uint8_t *out = static_cast<uint8_t *>(a.dst);
-    uint8_t *rec = out + a.p0 + off;
+    uint8_t *rec = deferred ? slots + b * DEFER_SLOT : out + a.p0 + off;
 
     if (tid == 0) {
         reinterpret_cast<uint32_t *>(rec)[0] = nnz;
         reinterpret_cast<uint32_t *>(rec)[1] = 0u;
-        reinterpret_cast<uint64_t *>(out + 64)[b + 1] = off + rbytes;
         for (uint64_t p = used; p < rbytes; p += 4)
             *reinterpret_cast<uint32_t *>(rec + p) = 0u;
-        if (b + 1 == a.nblocks) {
-            *reinterpret_cast<uint64_t *>(out + 56) = off + rbytes;
-            if (a.total)
-                *a.total = a.p0 + off + rbytes;
+        if (!deferred) {
+            reinterpret_cast<uint64_t *>(out + 64)[b + 1] = off + rbytes;
+            if (b + 1 == a.nblocks) {
+                *reinterpret_cast<uint64_t *>(out + 56) = off + rbytes;
+                if (a.total)
+                    *a.total = a.p0 + off + rbytes;
+            }
         }
     }
     uint64_t *mask = reinterpret_cast<uint64_t *>(rec + 8);
@@ -1497,6 +1517,118 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
 // the grid) clear its look-back flags and write its header (payload size 0
 // until its last block fills it), offset 0 and the zero pad between its
 // offset table and payload; a field without blocks gets its total here.
+// Fix-up after a forward with deferred records (one field): chunk c of
+// FIX_CHUNK blocks scans its record sizes, takes the sizes of all earlier
+// chunks by a look-back over chunk flags, writes the offsets of its blocks
+// and moves its deferred records from their slots into the stream.  Chunks
+// take tickets from a counter behind the flags, so every smaller chunk is
+// resident or done.
+size_t defer_sizes_bytes(uint64_t nblocks)
+{
+    const uint64_t nch = (nblocks + FIX_CHUNK - 1) / FIX_CHUNK;
+    return (size_t)(((nblocks * 4 + 7) & ~7ull) + 8 * (nch + 1));
+}
+
+__device__ __forceinline__ uint64_t *chunk_flags(uint32_t *sizes, uint64_t nblocks)
+{
+    return reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(sizes) + ((nblocks * 4 + 7) & ~7ull));
+}
+
+__global__ __launch_bounds__(256) void defer_scan_kernel(Queue q)
+{
+    constexpr int NT = 256, PER = FIX_CHUNK / NT;
+    __shared__ uint32_t s_scan[NT / 64 + 1];
+    __shared__ uint64_t s_chunk, s_base;
+    const FieldView a = field_view(q, 0);
+    ConstDesc *desc = (ConstDesc *)q.fields;
+    uint32_t *sizes = desc->sizes;
+    const uint64_t nb = a.nblocks;
+    const uint64_t nch = (nb + FIX_CHUNK - 1) / FIX_CHUNK;
+    uint64_t *cflags = chunk_flags(sizes, nb);
+    uint8_t *out = static_cast<uint8_t *>(a.dst);
+    const int tid = threadIdx.x;
+    while (true) {
+        if (tid == 0)
+            s_chunk = atomicAdd(reinterpret_cast<unsigned long long *>(cflags + nch), 1ull);
+        lds_barrier();
+        const uint64_t c = uniform64(s_chunk);
+        if (c >= nch)
+            break;
+        const uint64_t b0 = c * FIX_CHUNK + (uint64_t)tid * PER;
+        uint32_t sz[PER];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            sz[k] = b0 + k < nb ? sizes[b0 + k] & ~DEFER_BIT : 0u;
+            sum += sz[k];
+        }
+        const uint32_t pre = block_exclusive_scan<NT>(sum, s_scan);  // a chunk's records stay below 2^32 bytes
+        if (tid < 64) {
+            const uint64_t o = lookback_wave(cflags, c, s_scan[NT / 64], q.status, nullptr);
+            if (tid == 0)
+                s_base = o;
+        }
+        lds_barrier();
+        uint64_t run = s_base + pre;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const uint64_t b = b0 + k;
+            if (b < nb) {
+                run += sz[k];
+                reinterpret_cast<uint64_t *>(out + 64)[b + 1] = run;
+                if (b + 1 == nb) {
+                    *reinterpret_cast<uint64_t *>(out + 56) = run;
+                    if (a.total)
+                        *a.total = a.p0 + run;
+                }
+            }
+        }
+        lds_barrier();  // s_chunk, s_base are rewritten for the next chunk
+    }
+}
+
+// One wavefront per block: a deferred record moves from its slot to the
+// offset the scan wrote, 16 bytes a lane (4 when the stream is not 16-byte
+// aligned), every load issued before the stores.
+__global__ __launch_bounds__(256) void defer_copy_kernel(Queue q)
+{
+    const FieldView a = field_view(q, 0);
+    ConstDesc *desc = (ConstDesc *)q.fields;
+    const uint8_t *slots = desc->defer;
+    const uint32_t *sizes = desc->sizes;
+    const uint64_t b = (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (b >= a.nblocks)
+        return;
+    const uint32_t r = sizes[b];
+    if (!(r & DEFER_BIT))
+        return;
+    const uint32_t sz = r & ~DEFER_BIT;
+    const uint32_t lane = threadIdx.x % 64;
+    uint8_t *out = static_cast<uint8_t *>(a.dst);
+    const uint64_t off = reinterpret_cast<const uint64_t *>(out + 64)[b];
+    const uint8_t *src = slots + b * DEFER_SLOT;
+    uint8_t *dst = out + a.p0 + off;
+    if (((reinterpret_cast<uintptr_t>(out) | (uintptr_t)a.p0) & 15u) == 0) {
+        constexpr int K = DEFER_SLOT / (64 * 16);
+        uint4 v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t o = (uint32_t)(k * 64 + lane) * 16u;
+            if (o < sz)
+                v[k] = *reinterpret_cast<const uint4 *>(src + o);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t o = (uint32_t)(k * 64 + lane) * 16u;
+            if (o < sz)
+                *reinterpret_cast<uint4 *>(dst + o) = v[k];
+        }
+    } else {
+        for (uint32_t o = lane * 4u; o < sz; o += 64u * 4u)
+            *reinterpret_cast<uint32_t *>(dst + o) = *reinterpret_cast<const uint32_t *>(src + o);
+    }
+}
+
 __global__ void prep_kernel(Queue q, int forward)
 {
     const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1526,6 +1658,12 @@ __global__ void prep_kernel(Queue q, int forward)
     const uint64_t pad0 = 64 + 8 * (a.nblocks + 1);
     for (uint64_t p = pad0 + 4 * i0; p < a.p0; p += 4 * stride)
         *reinterpret_cast<uint32_t *>(out + p) = 0u;
+    if (a.sizes) {  // the fix-up's chunk flags and chunk counter
+        uint64_t *cf = chunk_flags(a.sizes, a.nblocks);
+        const uint64_t nch = (a.nblocks + FIX_CHUNK - 1) / FIX_CHUNK;
+        for (uint64_t i = i0; i <= nch; i += stride)
+            cf[i] = 0;
+    }
 }
 
 // OR the status words of a batch's classes (ticket, status pairs) into one.
@@ -1779,6 +1917,21 @@ int grid_cap(const KernelKey &key)
 hipError_t launch_fold_status(const uint32_t *counters, int nclass, uint32_t *status, hipStream_t st)
 {
     hipLaunchKernelGGL(fold_status_kernel, dim3(1), dim3(64), 0, st, counters, nclass, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_defer_fix(const Queue &q, hipStream_t st)
+{
+    const uint64_t nb = q.one.nblocks;
+    const uint64_t nch = (nb + FIX_CHUNK - 1) / FIX_CHUNK;
+    if (nch == 0)
+        return hipSuccess;
+    const uint64_t g = nch < 2048 ? nch : 2048;  // workgroups loop over chunk tickets
+    hipLaunchKernelGGL(defer_scan_kernel, dim3((uint32_t)g), dim3(256), 0, st, q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(defer_copy_kernel, dim3((uint32_t)((nb + 3) / 4)), dim3(256), 0, st, q);
     return hipGetLastError();
 }
 

@@ -135,3 +135,26 @@ def test_small_blocks_many_groups(codec, oracle, N, shape, dt):
     f = f.contiguous()
     for scheme in ("W4", "W4_li", "W3_ai"):
         whole_parity(codec, oracle, f, N, scheme, 1e-3 * fields.value_range(f), f"{N}^3 {dt} {scheme}")
+
+
+@pytest.mark.parametrize("layout", ["halves", "checker"])
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_deferred_and_direct_records(codec, oracle, dt, layout):
+    """32^3 blocks whose record fits a slot skip the look-back and are placed
+    by the fix-up; larger records look back through the sizes the deferred
+    ones published.  'halves': 320 smooth blocks (deferred) then 192 noisy
+    ones (direct), so the first direct block walks back over 320 published
+    sizes; 'checker': the two kinds alternate block by block."""
+    from paper_1903_07761_amd import fields
+
+    n = 256
+    smooth = fields.gaussian_bumps(n, 1911, dtype=dt)
+    rng = torch.Generator().manual_seed(1912)
+    noisy = smooth + 0.05 * torch.randn(n, n, n, generator=rng, dtype=torch.float64).to(dt)
+    if layout == "halves":
+        f = torch.cat([smooth[:160], noisy[160:]], dim=0)
+    else:
+        z, y, x = torch.meshgrid(torch.arange(n) // 32, torch.arange(n) // 32, torch.arange(n) // 32, indexing="ij")
+        f = torch.where(((x + y + z) % 2 == 0), smooth, noisy)
+    f = f.contiguous().cuda()
+    whole_parity(codec, oracle, f, 32, "W3_ai", 1e-3 * fields.value_range(f), f"deferred/direct {layout} {dt}")
