@@ -730,7 +730,7 @@ __device__ __forceinline__ void wave_lines(T *reg, int lane)
 // The 64 lines along x (AXIS 0) or y (AXIS 1) of SZ = 64 / N staged planes
 // (pitches 1, PX, PS), one per lane: lane = i + N j, i the other in-plane
 // coordinate, j the plane.
-template <typename T, int S, int N, int AXIS, int PX, int PS>
+template <typename T, int S, int N, int AXIS, int PX, int PS, bool INV = false>
 __device__ __forceinline__ void slab_lines(T *reg, int lane)
 {
     const int i = lane % N, j = lane / N;
@@ -740,7 +740,10 @@ __device__ __forceinline__ void slab_lines(T *reg, int lane)
 #pragma unroll
     for (int k = 0; k < N; ++k)
         v[k] = reg[base + k * stride];
-    line_fwd<T, S, N>(v);
+    if constexpr (INV)
+        line_inv<T, S, N>(v);
+    else
+        line_fwd<T, S, N>(v);
 #pragma unroll
     for (int k = 0; k < N; ++k)
         reg[base + k * stride] = v[k];
@@ -924,6 +927,133 @@ __global__ __launch_bounds__((64 * SmallGroup<T, N>::value)) void fwd_small_kern
                 const uint32_t rank = __builtin_amdgcn_readlane(pre, wi) + mbcnt(word);
                 buf_store(c[r][z], vr, rank * (uint32_t)sizeof(T));
             }
+        }
+    }
+}
+
+// ------------------------------------------------- inverse, 8^3 blocks
+
+// An 8^3 block decodes in well under a microsecond of work but through three
+// dependent memory round trips (record offsets, then its header and mask,
+// then its values), so a wavefront that decodes one block at a time mostly
+// waits.  Here each wavefront keeps IK blocks in flight: lane (x, y) owns the
+// z-column of every block, the offsets, nnz and the 8 mask words of a block
+// are uniform and come through scalar loads (the stream is read-only during
+// the call), so the prefix of each mask word is a scalar sum and needs no
+// LDS, and the value gathers of all IK blocks are issued together.  The
+// transforms then run one block after another through the wavefront's LDS
+// region (z-lines in VGPRs, y- then x-lines in LDS).  Blocks are independent:
+// wavefront w takes the ticket groups w, w + W, ... (W wavefronts in the
+// grid), with no counter.
+constexpr int IK = 4;             // 8^3 blocks in flight per wavefront
+constexpr int INV8_WAVES = 4;     // wavefronts per workgroup
+
+template <typename T, int S>
+__global__ __launch_bounds__(64 * INV8_WAVES) void inv_small8_kernel(Queue q)
+{
+    constexpr int N = 8, PX = 9, PS = 72;
+    constexpr uint32_t MASK_BYTES = 64;
+    using CU64 = const __attribute__((address_space(4))) uint64_t;
+    using CU32 = const __attribute__((address_space(4))) uint32_t;
+    __shared__ T lds[INV8_WAVES * N * PS];
+    const int lane = (int)lane_id();
+    const int wave = threadIdx.x / 64;
+    const int x = lane % N, y = lane / N;
+    T *reg = lds + wave * N * PS;
+    const uint64_t nw = (uint64_t)gridDim.x * INV8_WAVES;
+    for (uint64_t g = (uint64_t)blockIdx.x * INV8_WAVES + wave; g * IK < q.ntickets; g += nw) {
+        bool ok[IK];
+        uint32_t fld[IK];
+        uint64_t ob[IK];
+        CU64 *mk[IK];
+        const uint8_t *vals[IK];
+        uint32_t nnz[IK];
+        // headers: record offsets, then nnz and the mask, of every block
+#pragma unroll
+        for (int j = 0; j < IK; ++j) {
+            const uint64_t t = g * IK + j;
+            ok[j] = t < q.ntickets;
+            fld[j] = 0;
+            ob[j] = 0;
+            mk[j] = nullptr;
+            vals[j] = nullptr;
+            nnz[j] = 0;
+            if (ok[j]) {
+                fld[j] = __builtin_amdgcn_readfirstlane(field_of_ticket(q, t));
+                const FieldView a = field_view(q, fld[j]);
+                const uint64_t k = t - a.first;
+                const uint64_t b = uniform64(a.sel ? a.sel[2 * k] : k);  // the record this ticket decodes
+                ob[j] = uniform64(a.sel ? a.sel[2 * k + 1] : k);       // and the output block it fills
+                const uint8_t *in = static_cast<const uint8_t *>(a.src);
+                CU64 *offs = (CU64 *)(in + 64);
+                ok[j] = b < a.rblocks;
+                const uint64_t o0 = ok[j] ? offs[b] : 0, o1 = ok[j] ? offs[b + 1] : 0;
+                ok[j] = ok[j] && o1 >= o0 && o1 <= a.payload && o1 - o0 >= 8ull + MASK_BYTES;
+                if (ok[j]) {
+                    const uint8_t *rec = in + a.p0 + o0;
+                    nnz[j] = *(CU32 *)rec;
+                    const uint64_t used = 8ull + MASK_BYTES + (uint64_t)nnz[j] * sizeof(T);
+                    ok[j] = nnz[j] <= (uint32_t)(N * N * N) && ((used + 15ull) & ~15ull) == o1 - o0;
+                    mk[j] = (CU64 *)(rec + 8);
+                    vals[j] = rec + 8 + MASK_BYTES;
+                }
+                if (!ok[j] && lane == 0)
+                    report(q, fld[j], STATUS_FORMAT);
+            }
+        }
+        // gathers of every block: plane z's word is uniform, its prefix a scalar sum
+        T c[IK][N];
+#pragma unroll
+        for (int j = 0; j < IK; ++j) {
+            uint64_t w[N];
+            uint32_t pre = 0;
+#pragma unroll
+            for (int z = 0; z < N; ++z) {
+                w[z] = ok[j] ? mk[j][z] : 0ull;
+                pre += (uint32_t)__popcll(w[z]);
+            }
+            if (ok[j] && pre != nnz[j]) {
+                ok[j] = false;
+                if (lane == 0)
+                    report(q, fld[j], STATUS_FORMAT);
+            }
+            const rsrc_t vr = make_rsrc(vals[j], ok[j] ? nnz[j] * (uint32_t)sizeof(T) : 0u);
+            pre = 0;
+#pragma unroll
+            for (int z = 0; z < N; ++z) {
+                c[j][z] = T(0);
+                if ((w[z] >> lane) & 1ull)
+                    c[j][z] = buf_load<T>(vr, (pre + mbcnt(w[z])) * (uint32_t)sizeof(T));
+                pre += (uint32_t)__popcll(w[z]);
+            }
+        }
+        // transforms and stores, one block after another
+#pragma unroll
+        for (int j = 0; j < IK; ++j) {
+            if (!ok[j])
+                continue;
+            line_inv<T, S, N>(c[j]);
+#pragma unroll
+            for (int z = 0; z < N; ++z)
+                reg[z * PS + y * PX + x] = c[j][z];
+            wave_lds_sync();
+            slab_lines<T, S, N, 1, PX, PS, true>(reg, lane);  // y-lines
+            wave_lds_sync();
+            slab_lines<T, S, N, 0, PX, PS, true>(reg, lane);  // x-lines
+            wave_lds_sync();
+            const FieldView a = field_view(q, fld[j]);
+            const uint64_t b = ob[j];
+            const size_t plane = (size_t)a.nx * a.ny;
+            const uint32_t bx = (uint32_t)(b % a.nbx);
+            const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
+            const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
+            T *blk = static_cast<T *>(a.dst) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+            const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
+            const uint32_t lane_off = ((uint32_t)y * a.nx + (uint32_t)x) * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int z = 0; z < N; ++z)
+                buf_store(reg[z * PS + y * PX + x], make_rsrc(blk + (size_t)z * plane, slab_bytes), lane_off);
+            wave_lds_sync();  // the region is rewritten by the next block
         }
     }
 }
@@ -1828,8 +1958,24 @@ hipError_t launch_fwd(const KernelKey &key, const Queue &q, int grid, hipStream_
     }
 }
 
+template <typename T, int S>
+static hipError_t launch_inv8_t(const Queue &q, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((inv_small8_kernel<T, S>), dim3(grid), dim3(64 * INV8_WAVES), 0, st, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_inv(const KernelKey &key, const Queue &q, int grid, hipStream_t st)
 {
+    if (key.block == 8) {
+        if (key.elem_bytes == 4)
+            return key.scheme == W4 ? launch_inv8_t<float, W4>(q, grid, st)
+                 : key.scheme == W4LI ? launch_inv8_t<float, W4LI>(q, grid, st)
+                                      : launch_inv8_t<float, W3AI>(q, grid, st);
+        return key.scheme == W4 ? launch_inv8_t<double, W4>(q, grid, st)
+             : key.scheme == W4LI ? launch_inv8_t<double, W4LI>(q, grid, st)
+                                  : launch_inv8_t<double, W3AI>(q, grid, st);
+    }
     if (key.block == 64) {
         if (key.elem_bytes == 4) {
             switch (key.scheme) {
@@ -1880,6 +2026,14 @@ int occupancy(const KernelKey &key, bool inverse)
         } else {
             CZ_VARIANTS(double, 32, occupancy_t, (inverse))
         }
+    }
+    if (key.block == 8) {
+        int nb = 0;
+        const hipError_t e =
+            key.elem_bytes == 4
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, inv_small8_kernel<float, W3AI>, 64 * INV8_WAVES, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, inv_small8_kernel<double, W3AI>, 64 * INV8_WAVES, 0);
+        return e == hipSuccess ? nb : 0;
     }
     if (key.elem_bytes == 4) {
         CZ_DISPATCH(float, occupancy_t, (inverse))
