@@ -1739,19 +1739,19 @@ __global__ __launch_bounds__(256) void defer_copy_kernel(Queue q)
     const uint8_t *src = slots + b * DEFER_SLOT;
     uint8_t *dst = out + a.p0 + off;
     if (((reinterpret_cast<uintptr_t>(out) | (uintptr_t)a.p0) & 15u) == 0) {
+        using u4 = uint32_t __attribute__((ext_vector_type(4)));
         constexpr int K = DEFER_SLOT / (64 * 16);
-        uint4 v[K];
+        u4 v[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < K; ++k) {  // offsets past the record re-read its first bytes (the slot is whole)
             const uint32_t o = (uint32_t)(k * 64 + lane) * 16u;
-            if (o < sz)
-                v[k] = *reinterpret_cast<const uint4 *>(src + o);
+            v[k] = *reinterpret_cast<const u4 *>(src + (o < sz ? o : 0u));
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const uint32_t o = (uint32_t)(k * 64 + lane) * 16u;
             if (o < sz)
-                *reinterpret_cast<uint4 *>(dst + o) = v[k];
+                *reinterpret_cast<u4 *>(dst + o) = v[k];
         }
     } else {
         for (uint32_t o = lane * 4u; o < sz; o += 64u * 4u)

@@ -158,3 +158,25 @@ def test_deferred_and_direct_records(codec, oracle, dt, layout):
         f = torch.where(((x + y + z) % 2 == 0), smooth, noisy)
     f = f.contiguous().cuda()
     whole_parity(codec, oracle, f, 32, "W3_ai", 1e-3 * fields.value_range(f), f"deferred/direct {layout} {dt}")
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_deferred_records_into_an_offset_buffer(codec, oracle, dt):
+    """The stream may start at any 4-byte-aligned address: with the output 4
+    bytes into a buffer, the fix-up moves deferred records with 4-byte
+    accesses; the stream equals the oracle's and the bytes around it are
+    untouched."""
+    from paper_1903_07761_amd import _cz, fields
+
+    f = fields.gaussian_bumps(128, 1913, dtype=dt, device="cuda")  # smooth: records fit the slots
+    eps = 1e-3 * fields.value_range(f)
+    p = codec.params(f, 32, "W3_ai", eps)
+    cap = _cz.compress_bound(p)
+    buf = torch.full((cap + 32,), 0x5C, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    n = codec.ctx.compress(p, f.data_ptr(), buf.data_ptr() + 4, cap, stream=st)
+    torch.cuda.synchronize()
+    host = buf.cpu().numpy()
+    assert host[:4].tobytes() == b"\x5c" * 4
+    assert host[4 + n:].tobytes() == b"\x5c" * (cap + 28 - n)
+    assert host[4:4 + n].tobytes() == oracle.compress(f.cpu().numpy(), 32, "W3_ai", eps)
