@@ -453,7 +453,13 @@ int cz_reserve(cz_ctx *ctx, uint64_t max_blocks)
     if (max_blocks >= MAX_BLOCKS)
         return CZ_ERR_SHAPE;
     DeviceGuard guard(ctx->device);
-    return ctx->flags.ensure(std::max<uint64_t>(max_blocks, 1) * sizeof(uint64_t));
+    const uint64_t nb = std::max<uint64_t>(max_blocks, 1);
+    int rc = ctx->flags.ensure(nb * sizeof(uint64_t));
+    if (rc == CZ_OK)
+        rc = ctx->defer.ensure((size_t)nb * czk::DEFER_SLOT);
+    if (rc == CZ_OK)
+        rc = ctx->dsizes.ensure(czk::defer_sizes_bytes(nb));
+    return rc;
 }
 
 size_t cz_compress_bound(const cz_params *p)
