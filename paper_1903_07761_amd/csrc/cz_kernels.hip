@@ -1228,24 +1228,30 @@ __global__ __launch_bounds__(N *N / R, (InvWaves<T, N, Z, R>::value)) void inv_k
 // x- and y-lines run on chunks of z-planes staged through LDS (row pitch
 // n + 1), the finest level reading its rows straight from the field (forward)
 // or writing them straight to it (inverse); the z-lines run in registers,
-// one column per thread at a time, lanes along x; the coarse levels from
-// (N/2)^3 (float) or (N/4)^3 (double) down run entirely in LDS.  Full
-// workgroup barriers separate passes that communicate through the scratch
-// slot (they must order global memory).
+// one column per thread at a time, lanes along x; the levels from (N/4)^3
+// down run entirely in LDS.  The finest z-pass also decimates the finest
+// details (forward) or gathers them from the record (inverse), so the slot
+// never holds a dropped detail.  Full workgroup barriers separate passes that
+// communicate through the scratch slot (they must order global memory).
 
 template <int NT>
 __device__ __forceinline__ void gbarrier() { __syncthreads(); }
 
+// Consecutive mask words a wavefront handles at once in the scratch kernels'
+// per-word loops (decimation, record values, gather), their loads all in flight.
+constexpr int DEC_U = 16;
+
 template <typename T, int N>
 struct Big {
     static constexpr int NT = SCRATCH_THREADS;
-    static constexpr int TAIL = sizeof(T) == 4 ? N / 2 : N / 4;  // edge of the LDS-resident levels
+    static constexpr int TAIL = N / 4;  // edge of the LDS-resident levels
+    // mask words and their prefixes sit above the coarse levels' staging
+    // while the finest z-pass and the coarse levels run
+    static constexpr size_t WORDS_AT = 81920;
     static constexpr int WORDS = N * N * N / 64;
     static constexpr size_t CHUNK_BYTES = (sizeof(T) == 4 ? 8 : 4) * (size_t)N * (N + 1) * sizeof(T);
-    static constexpr size_t TAIL_BYTES = (size_t)TAIL * TAIL * (TAIL + 1) * sizeof(T);
     static constexpr size_t WORD_BYTES = (size_t)WORDS * (sizeof(uint64_t) + sizeof(uint32_t));
-    static constexpr size_t M1 = CHUNK_BYTES > TAIL_BYTES ? CHUNK_BYTES : TAIL_BYTES;
-    static constexpr size_t LDS_BYTES = M1 > WORD_BYTES ? M1 : WORD_BYTES;
+    static constexpr size_t LDS_BYTES = CHUNK_BYTES > WORDS_AT + WORD_BYTES ? CHUNK_BYTES : WORDS_AT + WORD_BYTES;
     // planes per LDS chunk at level n: the largest power of two that fits
     static constexpr int chunk(int n)
     {
@@ -1383,39 +1389,116 @@ __device__ __forceinline__ void tail_levels(T *blk, T *lds)
     }
 }
 
-// Forward transform of a 64^3 block: field rows -> scratch slot.
+// The finest z-lines of the forward with the decimation of the finest
+// details: once a column's z-line is transformed, every coefficient outside
+// the coarse octant [0, N/2)^3 is final, so its keep bit is taken here.  A
+// wavefront holds one row y (x = lane) of each plane, so one ballot per plane
+// gives the mask word of (z, y) (bits of the octant's x < N/2 left for the
+// coarse pass).  Only coefficients still needed go back to the slot: the
+// octant (the next level's input) and kept details.
 template <typename T, int S, int N, int NT>
-__device__ __forceinline__ void big_fwd(const T *src, size_t plane, size_t row, uint32_t cs, T *blk, T *lds)
+__device__ __forceinline__ void z_finest_dec(T *blk, const FieldView &a, uint64_t *s_words, bool &bad)
+{
+    static_assert(N == 64, "one row of a plane per wavefront");
+    constexpr int H = N / 2;
+    const uint32_t lane = lane_id();
+#pragma unroll 1
+    for (int l = threadIdx.x; l < N * N; l += NT) {
+        const int x = l % N, y = l / N;
+        T v[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            v[k] = blk[(size_t)k * N * N + y * N + x];
+        line_fwd<T, S, N>(v);
+#pragma unroll
+        for (int z = 0; z < N; ++z) {
+            const bool fin = x >= H || y >= H || z >= H;
+            const bool keep = fin && keep_test<T>(v[z], a);
+            bad |= fin && !finite(v[z]);
+            const uint64_t m = __ballot(keep);
+            if (lane == 0)
+                s_words[z * N + y] = m;
+            if (!fin || keep)
+                blk[(size_t)z * N * N + y * N + x] = v[z];
+        }
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ constexpr bool coarse_staging_below_words()
 {
     using B = Big<T, N>;
+    return (size_t)B::chunk(N / 2) * (N / 2) * (N / 2 + 1) * sizeof(T) <= B::WORDS_AT &&
+           (size_t)B::TAIL * B::TAIL * (B::TAIL + 1) * sizeof(T) <= B::WORDS_AT && B::TAIL == N / 4;
+}
+
+// Forward transform of a 64^3 block: field rows -> scratch slot, the finest
+// details decimated on the way (mask words of them in s_words).
+template <typename T, int S, int N, int NT>
+__device__ __forceinline__ void big_fwd(const T *src, size_t plane, size_t row, uint32_t cs, T *blk, T *lds,
+                                        const FieldView &a, uint64_t *s_words, bool &bad)
+{
+    using B = Big<T, N>;
+    static_assert(coarse_staging_below_words<T, N>(), "the coarse levels' staging stays below the mask words");
     xy_level<T, S, N, B::chunk(N), false, NT>(src, plane, row, cs, blk, (size_t)N * N, N, lds);
     gbarrier<NT>();
-    z_level<T, S, N, N, false, NT>(blk);
+    z_finest_dec<T, S, N, NT>(blk, a, s_words, bad);
     gbarrier<NT>();
-    if constexpr (B::TAIL < N / 2) {
-        xy_level<T, S, N / 2, B::chunk(N / 2), false, NT>(blk, (size_t)N * N, N, 1, blk, (size_t)N * N, N, lds);
-        gbarrier<NT>();
-        z_level<T, S, N, N / 2, false, NT>(blk);
-        gbarrier<NT>();
-    }
+    xy_level<T, S, N / 2, B::chunk(N / 2), false, NT>(blk, (size_t)N * N, N, 1, blk, (size_t)N * N, N, lds);
+    gbarrier<NT>();
+    z_level<T, S, N, N / 2, false, NT>(blk);
+    gbarrier<NT>();
     tail_levels<T, S, N, B::TAIL, false, NT>(blk, lds);
     gbarrier<NT>();
 }
 
-// Inverse transform of a 64^3 block: scratch slot -> field rows.
+// The finest z-lines of the inverse with the gather of the finest details
+// fused in: the coarse octant [0, N/2)^3 comes from the slot (the coarse
+// levels' output), every other coefficient straight from the record (kept:
+// its value at the rank that the mask word's prefix and the bits below it
+// give; dropped: 0).  The transformed columns go back to the slot whole.
 template <typename T, int S, int N, int NT>
-__device__ __forceinline__ void big_inv(T *blk, T *dst, size_t plane, size_t row, T *lds)
+__device__ __forceinline__ void z_finest_gather(T *blk, rsrc_t vr, const uint64_t *s_words, const uint32_t *s_pre)
+{
+    static_assert(N == 64, "one row of a plane per wavefront");
+    constexpr int H = N / 2;
+    const uint32_t lane = lane_id();
+#pragma unroll 1
+    for (int l = threadIdx.x; l < N * N; l += NT) {
+        const int x = l % N, y = l / N;
+        T v[N];
+#pragma unroll
+        for (int z = 0; z < N; ++z) {
+            const uint64_t m = s_words[z * N + y];
+            v[z] = T(0);
+            if (z < H && y < H && x < H)
+                v[z] = blk[(size_t)z * N * N + y * N + x];
+            else if ((m >> lane) & 1ull)
+                v[z] = buf_load<T>(vr, (s_pre[z * N + y] + mbcnt(m)) * (uint32_t)sizeof(T));
+        }
+        line_inv<T, S, N>(v);
+#pragma unroll
+        for (int z = 0; z < N; ++z)
+            blk[(size_t)z * N * N + y * N + x] = v[z];
+    }
+}
+
+// Inverse transform of a 64^3 block whose coarse octant has been gathered
+// into the scratch slot: slot -> field rows (the finest details from the
+// record, mask words and prefixes in s_words / s_pre).
+template <typename T, int S, int N, int NT>
+__device__ __forceinline__ void big_inv(T *blk, T *dst, size_t plane, size_t row, T *lds, rsrc_t vr,
+                                        const uint64_t *s_words, const uint32_t *s_pre)
 {
     using B = Big<T, N>;
+    static_assert(coarse_staging_below_words<T, N>(), "the coarse levels' staging stays below the mask words");
     tail_levels<T, S, N, B::TAIL, true, NT>(blk, lds);
     gbarrier<NT>();
-    if constexpr (B::TAIL < N / 2) {
-        z_level<T, S, N, N / 2, true, NT>(blk);
-        gbarrier<NT>();
-        xy_level<T, S, N / 2, B::chunk(N / 2), true, NT>(blk, (size_t)N * N, N, 1, blk, (size_t)N * N, N, lds);
-        gbarrier<NT>();
-    }
-    z_level<T, S, N, N, true, NT>(blk);
+    z_level<T, S, N, N / 2, true, NT>(blk);
+    gbarrier<NT>();
+    xy_level<T, S, N / 2, B::chunk(N / 2), true, NT>(blk, (size_t)N * N, N, 1, blk, (size_t)N * N, N, lds);
+    gbarrier<NT>();
+    z_finest_gather<T, S, N, NT>(blk, vr, s_words, s_pre);
     gbarrier<NT>();
     xy_level<T, S, N, B::chunk(N), true, NT>(blk, (size_t)N * N, N, 1, dst, plane, row, lds);
 }
@@ -1451,11 +1534,15 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
     constexpr int WORDS = N * N * N / 64;
     constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
     constexpr int WAVES = NT / 64;
-    // LDS: line staging during the transform, then mask words and prefixes
+    static_assert(WORDS % (WAVES * DEC_U) == 0, "whole runs of words per wavefront");
+    constexpr int H = N / 2;
+    // LDS: line staging during the transform; mask words and prefixes above
+    // the coarse levels' staging (the finest level's staging is done with
+    // before the first word is written)
     __shared__ __align__(16) uint8_t lds_raw[Big<T, N>::LDS_BYTES];
     T *lds = reinterpret_cast<T *>(lds_raw);
-    uint64_t *s_words = reinterpret_cast<uint64_t *>(lds_raw);
-    uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds_raw + WORDS * sizeof(uint64_t));
+    uint64_t *s_words = reinterpret_cast<uint64_t *>(lds_raw + Big<T, N>::WORDS_AT);
+    uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds_raw + Big<T, N>::WORDS_AT + WORDS * sizeof(uint64_t));
     __shared__ uint32_t s_scan[WAVES + 1];
     __shared__ uint64_t s_block;
     __shared__ uint32_t s_field;
@@ -1486,18 +1573,32 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
         const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
         const T *src = static_cast<const T *>(a.src) + ((size_t)bz * N * plane + (size_t)by * N * row + (size_t)bx * N * a.cs);
         bool bad = false;
-        big_fwd<T, S, N, NT>(src, plane, row, a.cs, blkS, lds);
+        big_fwd<T, S, N, NT>(src, plane, row, a.cs, blkS, lds, a, s_words, bad);
 
-        // decimation: wavefront w takes words w, w + WAVES, ...
-        for (int w = wave; w < WORDS; w += WAVES) {
-            const int qq = w * 64 + (int)lane;
-            const int x = qq % N, y = (qq / N) % N, z = qq / (N * N);
-            const T v = blkS[qq];
-            bad |= !finite(v);
-            const bool keep = (x < 4 && y < 4 && z < 4) || keep_test<T>(v, a);
-            const uint64_t m = __ballot(keep);
-            if (lane == 0)
-                s_words[w] = m;
+        // decimation of the coarse octant (x, y, z < N/2; the 4^3 corner always
+        // kept): row (z, y) of it is the low half of word z N + y.  Wavefront w
+        // takes the runs of U consecutive rows starting at U w, U (w + WAVES),
+        // ..., all U loads of a run in flight together.
+        static_assert(N == 64 && (H * H) % (WAVES * DEC_U) == 0, "whole runs of octant rows");
+        for (int r0 = wave * DEC_U; r0 < H * H; r0 += WAVES * DEC_U) {
+            T v[DEC_U];
+#pragma unroll
+            for (int u = 0; u < DEC_U; ++u) {
+                const int z = (r0 + u) / H, y = (r0 + u) % H;
+                v[u] = T(0);
+                if ((int)lane < H)
+                    v[u] = blkS[(size_t)z * N * N + y * N + (int)lane];
+            }
+#pragma unroll
+            for (int u = 0; u < DEC_U; ++u) {
+                const int z = (r0 + u) / H, y = (r0 + u) % H, x = (int)lane;
+                const bool in = x < H;
+                bad |= in && !finite(v[u]);
+                const bool keep = in && ((x < 4 && y < 4 && z < 4) || keep_test<T>(v[u], a));
+                const uint64_t m = __ballot(keep);
+                if (lane == 0)
+                    s_words[z * N + y] |= m;
+            }
         }
         if (bad)
             s_bad = 1;
@@ -1532,10 +1633,22 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
         for (int w = tid; w < WORDS; w += NT)
             mask[w] = s_words[w];
         const rsrc_t vr = make_rsrc(rec + 8 + MASK_BYTES, nnz * (uint32_t)sizeof(T));
-        for (int w = wave; w < WORDS; w += WAVES) {
-            const uint64_t m = s_words[w];
-            if ((m >> lane) & 1ull)
-                buf_store(blkS[w * 64 + (int)lane], vr, (s_pre[w] + mbcnt(m)) * (uint32_t)sizeof(T));
+        // kept values from the slot into the record, runs of U words a
+        // wavefront, all U loads of a run in flight together
+        for (int w0 = wave * DEC_U; w0 < WORDS; w0 += WAVES * DEC_U) {
+            uint64_t m[DEC_U];
+            T v[DEC_U];
+#pragma unroll
+            for (int u = 0; u < DEC_U; ++u) {
+                m[u] = s_words[w0 + u];
+                v[u] = T(0);
+                if ((m[u] >> lane) & 1ull)
+                    v[u] = blkS[(w0 + u) * 64 + (int)lane];
+            }
+#pragma unroll
+            for (int u = 0; u < DEC_U; ++u)
+                if ((m[u] >> lane) & 1ull)
+                    buf_store(v[u], vr, (s_pre[w0 + u] + mbcnt(m[u])) * (uint32_t)sizeof(T));
         }
         gbarrier<NT>();
     }
@@ -1548,11 +1661,14 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
     constexpr int WORDS = N * N * N / 64;
     constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
     constexpr int WAVES = NT / 64;
-    // LDS: mask words and prefixes while unpacking, then line staging
+    static_assert(WORDS % (WAVES * DEC_U) == 0 && WORDS % NT == 0, "whole runs of words per wavefront");
+    constexpr int H = N / 2;
+    // LDS: line staging; mask words and prefixes above the coarse levels'
+    // staging until the finest z-pass has read them
     __shared__ __align__(16) uint8_t lds_raw[Big<T, N>::LDS_BYTES];
     T *lds = reinterpret_cast<T *>(lds_raw);
-    uint64_t *s_words = reinterpret_cast<uint64_t *>(lds_raw);
-    uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds_raw + WORDS * sizeof(uint64_t));
+    uint64_t *s_words = reinterpret_cast<uint64_t *>(lds_raw + Big<T, N>::WORDS_AT);
+    uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds_raw + Big<T, N>::WORDS_AT + WORDS * sizeof(uint64_t));
     __shared__ uint32_t s_scan[WAVES + 1];
     __shared__ uint64_t s_block;
     __shared__ uint32_t s_field;
@@ -1612,8 +1728,15 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
         const uint32_t nnz = *reinterpret_cast<const uint32_t *>(rec);
         const uint64_t *mask = reinterpret_cast<const uint64_t *>(rec + 8);
         const rsrc_t vr = make_rsrc(rec + 8 + MASK_BYTES, nnz * (uint32_t)sizeof(T));
-        for (int w = tid; w < WORDS; w += NT)
-            s_words[w] = mask[w];
+        {
+            uint64_t mw[WORDS / NT];
+#pragma unroll
+            for (int k = 0; k < WORDS / NT; ++k)
+                mw[k] = mask[tid + k * NT];
+#pragma unroll
+            for (int k = 0; k < WORDS / NT; ++k)
+                s_words[tid + k * NT] = mw[k];
+        }
         gbarrier<NT>();
         const uint32_t total = scan_words<NT, WORDS>(s_words, s_pre, s_scan);
         gbarrier<NT>();
@@ -1623,19 +1746,33 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void inv_scratch_kernel(Queue q)
             gbarrier<NT>();
             continue;
         }
-        for (int w = wave; w < WORDS; w += WAVES) {
-            const uint64_t m = s_words[w];
-            T v = T(0);
-            if ((m >> lane) & 1ull)
-                v = buf_load<T>(vr, (s_pre[w] + mbcnt(m)) * (uint32_t)sizeof(T));
-            blkS[w * 64 + (int)lane] = v;
+        // gather of the coarse octant: row (z, y) of it (x = lane < N/2) is
+        // the low half of word z N + y; runs of U rows a wavefront, their
+        // loads in flight together
+        static_assert(N == 64 && (H * H) % (WAVES * DEC_U) == 0, "whole runs of octant rows");
+        for (int r0 = wave * DEC_U; r0 < H * H; r0 += WAVES * DEC_U) {
+            T v[DEC_U];
+#pragma unroll
+            for (int u = 0; u < DEC_U; ++u) {
+                const int w = ((r0 + u) / H) * N + (r0 + u) % H;
+                const uint64_t m = s_words[w];
+                v[u] = T(0);
+                if ((int)lane < H && ((m >> lane) & 1ull))
+                    v[u] = buf_load<T>(vr, (s_pre[w] + mbcnt(m)) * (uint32_t)sizeof(T));
+            }
+#pragma unroll
+            for (int u = 0; u < DEC_U; ++u) {
+                const int z = (r0 + u) / H, y = (r0 + u) % H;
+                if ((int)lane < H)
+                    blkS[(size_t)z * N * N + y * N + (int)lane] = v[u];
+            }
         }
         gbarrier<NT>();
         const uint32_t bx = (uint32_t)(b % a.nbx);
         const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
         const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
         T *dst = static_cast<T *>(a.dst) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
-        big_inv<T, S, N, NT>(blkS, dst, plane, a.nx, lds);
+        big_inv<T, S, N, NT>(blkS, dst, plane, a.nx, lds, vr, s_words, s_pre);
         gbarrier<NT>();
     }
 }

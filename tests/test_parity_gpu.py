@@ -173,19 +173,21 @@ def test_threshold_tie(codec, oracle):
         assert gpu_compress(codec, B, N, "W4", eps) == oracle.compress(B, N, "W4", eps)
 
 
-def test_nonfinite_input_is_an_error(codec):
+@pytest.mark.parametrize("N", [8, 16, 32, 64])
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_nonfinite_input_is_an_error(codec, N, dt):
     from paper_1903_07761_amd import CzError, _cz
 
-    say("[edge] NaN input")
-    t = torch.ones((32, 32, 32), dtype=torch.float32, device="cuda")
-    t[5, 6, 7] = float("nan")
-    with pytest.raises(CzError) as e:
-        codec.compress(t, 32, "W4", 0.1)
-    assert e.value.code == _cz.ERR_NONFINITE
-    t[5, 6, 7] = float("inf")
-    with pytest.raises(CzError) as e:
-        codec.compress(t, 32, "W4", 0.1)
-    assert e.value.code == _cz.ERR_NONFINITE
+    say(f"[edge] NaN/inf input N={N} {dt}")
+    t = torch.ones((64, 64, 64), dtype=dt, device="cuda")
+    for pos in ((5, 6, 7), (63, 62, 61)):  # coarse corner / finest details of the last block
+        for bad in (float("nan"), float("inf"), float("-inf")):
+            t[pos] = bad
+            with pytest.raises(CzError) as e:
+                codec.compress(t, N, "W4", 0.1)
+            assert e.value.code == _cz.ERR_NONFINITE
+            t[pos] = 1.0
+    codec.compress(t, N, "W4", 0.1)  # clean again: no error
 
 
 def test_capacity_and_shape_errors(codec):
