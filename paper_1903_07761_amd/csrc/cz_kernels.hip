@@ -1237,6 +1237,10 @@ __global__ __launch_bounds__(N *N / R, (InvWaves<T, N, Z, R>::value)) void inv_k
 template <int NT>
 __device__ __forceinline__ void gbarrier() { __syncthreads(); }
 
+// Elements a thread moves at once between global memory and LDS in the
+// scratch kernels' x/y passes and LDS-resident levels.
+constexpr int XY_U = 8;
+
 // Consecutive mask words a wavefront handles at once in the scratch kernels'
 // per-word loops (decimation, record values, gather), their loads all in flight.
 constexpr int DEC_U = 16;
@@ -1270,11 +1274,35 @@ __device__ __forceinline__ void xy_level(const T *src, size_t sps, size_t srs, u
                                          size_t drs, T *lds)
 {
     constexpr int PX = n + 1, PS = n * PX;
+    static_assert(ZC * n * n % (NT * XY_U) == 0, "whole batches of elements per thread");
     for (int z0 = 0; z0 < n; z0 += ZC) {
+        if constexpr (!INV) {
+            // forward: XY_U loads in flight, then their LDS writes (the
+            // scheduling barrier keeps the compiler from pairing each load
+            // with its write, one round trip per element, when the kernel's
+            // registers look scarce)
+            for (int e0 = threadIdx.x; e0 < ZC * n * n; e0 += NT * XY_U) {
+                T t[XY_U];
+#pragma unroll
+                for (int u = 0; u < XY_U; ++u) {
+                    const int e = e0 + u * NT;
+                    const int x = e % n, y = (e / n) % n, j = e / (n * n);
+                    t[u] = src[(size_t)(z0 + j) * sps + (size_t)y * srs + (size_t)x * ses];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < XY_U; ++u) {
+                    const int e = e0 + u * NT;
+                    const int x = e % n, y = (e / n) % n, j = e / (n * n);
+                    lds[j * PS + y * PX + x] = t[u];
+                }
+            }
+        } else {
 #pragma unroll 8
-        for (int e = threadIdx.x; e < ZC * n * n; e += NT) {
-            const int x = e % n, y = (e / n) % n, j = e / (n * n);
-            lds[j * PS + y * PX + x] = src[(size_t)(z0 + j) * sps + (size_t)y * srs + (size_t)x * ses];
+            for (int e = threadIdx.x; e < ZC * n * n; e += NT) {
+                const int x = e % n, y = (e / n) % n, j = e / (n * n);
+                lds[j * PS + y * PX + x] = src[(size_t)(z0 + j) * sps + (size_t)y * srs + (size_t)x * ses];
+            }
         }
         lds_barrier();
         if constexpr (!INV) {
