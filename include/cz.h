@@ -48,7 +48,9 @@
  *   as +0.0.
  *
  * Blocks up to 32^3 stay on chip (VGPRs + LDS); 64^3 blocks (1 MiB float,
- * 2 MiB double) are staged in a per-workgroup scratch slot the context owns.
+ * 2 MiB double) are staged in per-workgroup scratch slots the context owns
+ * (two per workgroup: one block is transformed while the previous one waits
+ * for its offset).
  *
  * Conventions.  Every pointer named d_* is device memory of the context's
  * device, owned by the caller; the library keeps none of them after a call

@@ -236,10 +236,7 @@ uint64_t fwd_tickets(const czk::KernelKey &key, uint64_t nb)
     return (nb + g - 1) / g;
 }
 
-size_t scratch_need(const czk::KernelKey &key, int grid)
-{
-    return key.block == 64 ? (size_t)grid * 64 * 64 * 64 * key.elem_bytes : 0;
-}
+size_t scratch_need(const czk::KernelKey &key, int grid) { return czk::scratch_bytes(key, grid); }
 
 // Group the fields of a batch into classes (block size, precision, scheme,
 // variant), each with a ticket range, a grid and its own 64^3 scratch slots.

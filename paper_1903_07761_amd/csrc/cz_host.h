@@ -249,7 +249,7 @@ struct cz_ctx {
     czk::CzWork *work = nullptr;    // device: ticket, status, total of plain calls
     czk::CzWork *pinned = nullptr;  // host-pinned mirror for synchronous reads
     czh::DevBuf flags;                   // plain calls: look-back flags
-    czh::DevBuf scratch;                 // plain calls on 64^3 blocks: one slot per resident workgroup
+    czh::DevBuf scratch;                 // plain calls on 64^3 blocks: two slots per resident workgroup
     czh::DevBuf defer;                   // plain 32^3 compress: a record slot per block (deferred records)
     czh::DevBuf dsizes;                  // plain 32^3 compress: record sizes and the fix-up's chunk flags
     czk::FieldDesc *one = nullptr;  // device: the descriptor of a plain call (published by its prep kernel)

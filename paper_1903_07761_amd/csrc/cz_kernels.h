@@ -102,5 +102,7 @@ uint32_t fwd_blocks_per_ticket(const KernelKey &key);
 int variant_count(uint32_t block, uint32_t elem_bytes);
 // Upper bound on the workgroups of a launch (0: none).
 int grid_cap(const KernelKey &key);
+// Scratch bytes a launch of grid workgroups needs (N = 64; else 0).
+size_t scratch_bytes(const KernelKey &key, int grid);
 
 }  // namespace czk

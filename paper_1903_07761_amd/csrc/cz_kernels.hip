@@ -1555,22 +1555,38 @@ __device__ __forceinline__ uint32_t scan_words(const uint64_t *s_words, uint32_t
     return s_w[NT / 64];
 }
 
+// The 64^3 forward is persistent with two blocks in flight per workgroup:
+// block k is transformed, decimated and its record size published in one
+// slot, then block k-1's look-back is resolved and its record written from
+// the other slot.  A record's offset waits for every earlier block's size;
+// resolving it one block later gives those blocks a whole block's time to
+// publish instead of exposing the spread of their finishing times.  Mask
+// words and prefixes of a block wait in a side area beside its slot while the
+// next block's transform uses the LDS.  No wait is on a later ticket: every
+// earlier ticket's size is published before its holder waits on anything.
 template <typename T, int N, int S>
 __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
 {
+    using B = Big<T, N>;
     constexpr int NT = SCRATCH_THREADS;
     constexpr int WORDS = N * N * N / 64;
     constexpr uint32_t MASK_BYTES = (uint32_t)(N * N * N / 8);
     constexpr int WAVES = NT / 64;
-    static_assert(WORDS % (WAVES * DEC_U) == 0, "whole runs of words per wavefront");
+    static_assert(WORDS % (WAVES * DEC_U) == 0 && WORDS % NT == 0, "whole runs of words per wavefront");
+    static_assert(B::WORD_BYTES <= B::WORDS_AT, "two blocks' mask words fit the LDS side by side");
     constexpr int H = N / 2;
-    // LDS: line staging during the transform; mask words and prefixes above
-    // the coarse levels' staging (the finest level's staging is done with
-    // before the first word is written)
-    __shared__ __align__(16) uint8_t lds_raw[Big<T, N>::LDS_BYTES];
+    constexpr int K = WORDS / NT;  // words per thread in scan_words' layout
+    constexpr size_t SLOT = (size_t)N * N * N;
+    // LDS: line staging during the transform; the current block's mask words
+    // and prefixes above the coarse levels' staging (the finest level's
+    // staging is done with before the first word is written); the previous
+    // block's, reloaded for its record, at the bottom
+    __shared__ __align__(16) uint8_t lds_raw[B::LDS_BYTES];
     T *lds = reinterpret_cast<T *>(lds_raw);
-    uint64_t *s_words = reinterpret_cast<uint64_t *>(lds_raw + Big<T, N>::WORDS_AT);
-    uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds_raw + Big<T, N>::WORDS_AT + WORDS * sizeof(uint64_t));
+    uint64_t *s_words = reinterpret_cast<uint64_t *>(lds_raw + B::WORDS_AT);
+    uint32_t *s_pre = reinterpret_cast<uint32_t *>(lds_raw + B::WORDS_AT + WORDS * sizeof(uint64_t));
+    uint64_t *p_words = reinterpret_cast<uint64_t *>(lds_raw);
+    uint32_t *p_pre = reinterpret_cast<uint32_t *>(lds_raw + WORDS * sizeof(uint64_t));
     __shared__ uint32_t s_scan[WAVES + 1];
     __shared__ uint64_t s_block;
     __shared__ uint32_t s_field;
@@ -1580,8 +1596,16 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
     const int tid = threadIdx.x;
     const uint32_t lane = lane_id();
     const int wave = tid / 64;
-    T *blkS = static_cast<T *>(q.scratch) + (size_t)blockIdx.x * N * N * N;
+    // two slots per workgroup, then (after every workgroup's slots) a side
+    // area per slot for its block's mask words and prefixes
+    T *slots = static_cast<T *>(q.scratch) + (size_t)blockIdx.x * 2 * SLOT;
+    uint8_t *sides = reinterpret_cast<uint8_t *>(static_cast<T *>(q.scratch) + (size_t)gridDim.x * 2 * SLOT) +
+                     (size_t)blockIdx.x * 2 * B::WORD_BYTES;
 
+    int cur = 0;             // slot of the block taken this iteration
+    bool have_prev = false;  // a block waits in the other slot for its record
+    uint32_t pf = 0, pnnz = 0;
+    uint64_t pb = 0;
     while (true) {
         if (tid == 0) {
             const uint64_t t = atomicAdd(q.ticket, 1u);
@@ -1591,94 +1615,151 @@ __global__ __launch_bounds__(SCRATCH_THREADS) void fwd_scratch_kernel(Queue q)
         }
         gbarrier<NT>();
         const uint64_t t = uniform64(s_block);
-        if (t >= q.ntickets)
-            break;
-        const FieldView a = field_view(q, s_field);
-        const uint64_t b = t - a.first;
-        const size_t row = (size_t)a.nx * a.cs, plane = row * a.ny;
-        const uint32_t bx = (uint32_t)(b % a.nbx);
-        const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
-        const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
-        const T *src = static_cast<const T *>(a.src) + ((size_t)bz * N * plane + (size_t)by * N * row + (size_t)bx * N * a.cs);
-        bool bad = false;
-        big_fwd<T, S, N, NT>(src, plane, row, a.cs, blkS, lds, a, s_words, bad);
+        const bool more = t < q.ntickets;
+        const uint32_t f = s_field;
+        uint64_t b = 0;
+        uint32_t nnz = 0;
+        if (more) {
+            if (have_prev) {
+                // this block's transform reuses the LDS: the waiting block's
+                // mask words and prefixes go to its side area first
+                uint64_t *sw = reinterpret_cast<uint64_t *>(sides + (size_t)(cur ^ 1) * B::WORD_BYTES);
+                uint32_t *sp = reinterpret_cast<uint32_t *>(sw + WORDS);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    sw[tid * K + k] = s_words[tid * K + k];
+                    sp[tid * K + k] = s_pre[tid * K + k];
+                }
+                gbarrier<NT>();
+            }
+            const FieldView a = field_view(q, f);
+            b = t - a.first;
+            T *blkS = slots + (size_t)cur * SLOT;
+            const size_t row = (size_t)a.nx * a.cs, plane = row * a.ny;
+            const uint32_t bx = (uint32_t)(b % a.nbx);
+            const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
+            const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
+            const T *src = static_cast<const T *>(a.src) +
+                           ((size_t)bz * N * plane + (size_t)by * N * row + (size_t)bx * N * a.cs);
+            bool bad = false;
+            big_fwd<T, S, N, NT>(src, plane, row, a.cs, blkS, lds, a, s_words, bad);
 
-        // decimation of the coarse octant (x, y, z < N/2; the 4^3 corner always
-        // kept): row (z, y) of it is the low half of word z N + y.  Wavefront w
-        // takes the runs of U consecutive rows starting at U w, U (w + WAVES),
-        // ..., all U loads of a run in flight together.
-        static_assert(N == 64 && (H * H) % (WAVES * DEC_U) == 0, "whole runs of octant rows");
-        for (int r0 = wave * DEC_U; r0 < H * H; r0 += WAVES * DEC_U) {
-            T v[DEC_U];
+            // decimation of the coarse octant (x, y, z < N/2; the 4^3 corner
+            // always kept): row (z, y) of it is the low half of word z N + y.
+            // Wavefront w takes the runs of U consecutive rows starting at
+            // U w, U (w + WAVES), ..., all U loads of a run in flight together.
+            static_assert(N == 64 && (H * H) % (WAVES * DEC_U) == 0, "whole runs of octant rows");
+            for (int r0 = wave * DEC_U; r0 < H * H; r0 += WAVES * DEC_U) {
+                T v[DEC_U];
 #pragma unroll
-            for (int u = 0; u < DEC_U; ++u) {
-                const int z = (r0 + u) / H, y = (r0 + u) % H;
-                v[u] = T(0);
-                if ((int)lane < H)
-                    v[u] = blkS[(size_t)z * N * N + y * N + (int)lane];
+                for (int u = 0; u < DEC_U; ++u) {
+                    const int z = (r0 + u) / H, y = (r0 + u) % H;
+                    v[u] = T(0);
+                    if ((int)lane < H)
+                        v[u] = blkS[(size_t)z * N * N + y * N + (int)lane];
+                }
+#pragma unroll
+                for (int u = 0; u < DEC_U; ++u) {
+                    const int z = (r0 + u) / H, y = (r0 + u) % H, x = (int)lane;
+                    const bool in = x < H;
+                    bad |= in && !finite(v[u]);
+                    const bool keep = in && ((x < 4 && y < 4 && z < 4) || keep_test<T>(v[u], a));
+                    const uint64_t m = __ballot(keep);
+                    if (lane == 0)
+                        s_words[z * N + y] |= m;
+                }
             }
+            if (bad)
+                s_bad = 1;
+            gbarrier<NT>();
+            if (tid == 0 && s_bad)
+                report(q, f, STATUS_NONFINITE);
+            nnz = scan_words<NT, WORDS>(s_words, s_pre, s_scan);
+            const uint64_t rbytes = (8ull + MASK_BYTES + (uint64_t)nnz * sizeof(T) + 15ull) & ~15ull;
+            if (tid < 64)
+                lookback_publish(a.flags, b, rbytes);
+        }
+        if (have_prev) {
+            // the previous block: its words and prefixes (back in LDS from
+            // its side area if a transform ran since, else still in place),
+            // its offset from the look-back, then its record
+            const uint64_t *pw = s_words;
+            const uint32_t *pp = s_pre;
+            if (more) {
+                const uint64_t *sw = reinterpret_cast<const uint64_t *>(sides + (size_t)(cur ^ 1) * B::WORD_BYTES);
+                const uint32_t *sp = reinterpret_cast<const uint32_t *>(sw + WORDS);
+                uint64_t mw[K];
+                uint32_t mp[K];
 #pragma unroll
-            for (int u = 0; u < DEC_U; ++u) {
-                const int z = (r0 + u) / H, y = (r0 + u) % H, x = (int)lane;
-                const bool in = x < H;
-                bad |= in && !finite(v[u]);
-                const bool keep = in && ((x < 4 && y < 4 && z < 4) || keep_test<T>(v[u], a));
-                const uint64_t m = __ballot(keep);
-                if (lane == 0)
-                    s_words[z * N + y] |= m;
+                for (int k = 0; k < K; ++k) {
+                    mw[k] = sw[tid * K + k];
+                    mp[k] = sp[tid * K + k];
+                }
+                gbarrier<NT>();  // every thread is done with the LDS below
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    p_words[tid * K + k] = mw[k];
+                    p_pre[tid * K + k] = mp[k];
+                }
+                pw = p_words;
+                pp = p_pre;
+            }
+            const FieldView a = field_view(q, pf);
+            const uint64_t used = 8ull + MASK_BYTES + (uint64_t)pnnz * sizeof(T);
+            const uint64_t rbytes = (used + 15ull) & ~15ull;
+            if (tid < 64) {
+                const uint64_t o =
+                    lookback_resolve(a.flags, pb, rbytes, q.status, q.fstatus ? q.fstatus + pf : nullptr);
+                if (tid == 0)
+                    s_off = o;
+            }
+            gbarrier<NT>();
+            const uint64_t off = s_off;
+            const T *blkP = slots + (size_t)(cur ^ 1) * SLOT;
+            uint8_t *out = static_cast<uint8_t *>(a.dst);
+            uint8_t *rec = out + a.p0 + off;
+            if (tid == 0) {
+                reinterpret_cast<uint32_t *>(rec)[0] = pnnz;
+                reinterpret_cast<uint32_t *>(rec)[1] = 0u;
+                reinterpret_cast<uint64_t *>(out + 64)[pb + 1] = off + rbytes;
+                for (uint64_t p = used; p < rbytes; p += 4)
+                    *reinterpret_cast<uint32_t *>(rec + p) = 0u;
+                if (pb + 1 == a.nblocks) {
+                    *reinterpret_cast<uint64_t *>(out + 56) = off + rbytes;
+                    if (a.total)
+                        *a.total = a.p0 + off + rbytes;
+                }
+            }
+            uint64_t *mask = reinterpret_cast<uint64_t *>(rec + 8);
+            for (int w = tid; w < WORDS; w += NT)
+                mask[w] = pw[w];
+            const rsrc_t vr = make_rsrc(rec + 8 + MASK_BYTES, pnnz * (uint32_t)sizeof(T));
+            // kept values from the slot into the record, runs of U words a
+            // wavefront, all U loads of a run in flight together
+            for (int w0 = wave * DEC_U; w0 < WORDS; w0 += WAVES * DEC_U) {
+                uint64_t m[DEC_U];
+                T v[DEC_U];
+#pragma unroll
+                for (int u = 0; u < DEC_U; ++u) {
+                    m[u] = pw[w0 + u];
+                    v[u] = T(0);
+                    if ((m[u] >> lane) & 1ull)
+                        v[u] = blkP[(w0 + u) * 64 + (int)lane];
+                }
+#pragma unroll
+                for (int u = 0; u < DEC_U; ++u)
+                    if ((m[u] >> lane) & 1ull)
+                        buf_store(v[u], vr, (pp[w0 + u] + mbcnt(m[u])) * (uint32_t)sizeof(T));
             }
         }
-        if (bad)
-            s_bad = 1;
         gbarrier<NT>();
-        if (tid == 0 && s_bad)
-            report(q, s_field, STATUS_NONFINITE);
-        const uint32_t nnz = scan_words<NT, WORDS>(s_words, s_pre, s_scan);
-        const uint64_t used = 8ull + MASK_BYTES + (uint64_t)nnz * sizeof(T);
-        const uint64_t rbytes = (used + 15ull) & ~15ull;
-        if (tid < 64) {
-            const uint64_t o = lookback_wave(a.flags, b, rbytes, q.status, q.fstatus ? q.fstatus + s_field : nullptr);
-            if (tid == 0)
-                s_off = o;
-        }
-        gbarrier<NT>();
-        const uint64_t off = s_off;
-        uint8_t *out = static_cast<uint8_t *>(a.dst);
-        uint8_t *rec = out + a.p0 + off;
-        if (tid == 0) {
-            reinterpret_cast<uint32_t *>(rec)[0] = nnz;
-            reinterpret_cast<uint32_t *>(rec)[1] = 0u;
-            reinterpret_cast<uint64_t *>(out + 64)[b + 1] = off + rbytes;
-            for (uint64_t p = used; p < rbytes; p += 4)
-                *reinterpret_cast<uint32_t *>(rec + p) = 0u;
-            if (b + 1 == a.nblocks) {
-                *reinterpret_cast<uint64_t *>(out + 56) = off + rbytes;
-                if (a.total)
-                    *a.total = a.p0 + off + rbytes;
-            }
-        }
-        uint64_t *mask = reinterpret_cast<uint64_t *>(rec + 8);
-        for (int w = tid; w < WORDS; w += NT)
-            mask[w] = s_words[w];
-        const rsrc_t vr = make_rsrc(rec + 8 + MASK_BYTES, nnz * (uint32_t)sizeof(T));
-        // kept values from the slot into the record, runs of U words a
-        // wavefront, all U loads of a run in flight together
-        for (int w0 = wave * DEC_U; w0 < WORDS; w0 += WAVES * DEC_U) {
-            uint64_t m[DEC_U];
-            T v[DEC_U];
-#pragma unroll
-            for (int u = 0; u < DEC_U; ++u) {
-                m[u] = s_words[w0 + u];
-                v[u] = T(0);
-                if ((m[u] >> lane) & 1ull)
-                    v[u] = blkS[(w0 + u) * 64 + (int)lane];
-            }
-#pragma unroll
-            for (int u = 0; u < DEC_U; ++u)
-                if ((m[u] >> lane) & 1ull)
-                    buf_store(v[u], vr, (s_pre[w0 + u] + mbcnt(m[u])) * (uint32_t)sizeof(T));
-        }
-        gbarrier<NT>();
+        if (!more)
+            break;
+        have_prev = true;
+        pf = f;
+        pb = b;
+        pnnz = nnz;
+        cur ^= 1;
     }
 }
 
@@ -2226,6 +2307,16 @@ int variant_count(uint32_t block, uint32_t elem_bytes)
     if (block == 32)
         return 3;
     return block == 16 ? 2 : block == 64 ? 3 : 1;
+}
+
+size_t scratch_bytes(const KernelKey &key, int grid)
+{
+    if (key.block != 64)
+        return 0;
+    // forward: two slots and two side areas (mask words and prefixes) per
+    // workgroup; the inverse uses the first grid slots
+    const size_t words = (size_t)64 * 64 * 64 / 64;
+    return (size_t)grid * 2 * ((size_t)64 * 64 * 64 * key.elem_bytes + words * (sizeof(uint64_t) + sizeof(uint32_t)));
 }
 
 int grid_cap(const KernelKey &key)

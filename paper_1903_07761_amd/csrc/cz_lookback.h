@@ -35,16 +35,22 @@ __device__ __forceinline__ void atomic_store_u64(uint64_t *p, uint64_t v)
 // predecessors; the lanes up to the nearest inclusive prefix must all have
 // published before their sizes are summed.  Every wait is bounded: on
 // exhaustion the status word gets STATUS_TIMEOUT.
-__device__ inline uint64_t lookback_wave(uint64_t *flags, uint64_t b, uint64_t size, uint32_t *status, uint32_t *fstatus)
+//
+// lookback_publish and lookback_resolve are its two halves, for callers that
+// do other work in between (the predecessors then have more time to publish):
+// publish first, resolve later; block 0 publishes its inclusive prefix at once.
+__device__ inline void lookback_publish(uint64_t *flags, uint64_t b, uint64_t size)
+{
+    if (__lane_id() == 0)
+        atomic_store_u64(&flags[b], (b == 0 ? FLAG_INC : FLAG_AGG) | size);
+}
+
+__device__ inline uint64_t lookback_resolve(uint64_t *flags, uint64_t b, uint64_t size, uint32_t *status,
+                                            uint32_t *fstatus)
 {
     const uint32_t lane = __lane_id();
-    if (b == 0) {
-        if (lane == 0)
-            atomic_store_u64(&flags[0], FLAG_INC | size);
+    if (b == 0)
         return 0;
-    }
-    if (lane == 0)
-        atomic_store_u64(&flags[b], FLAG_AGG | size);
     uint64_t excl = 0;
     uint64_t top = b;  // this step covers blocks [top - 64, top)
     uint32_t spins = 0;
@@ -80,6 +86,12 @@ __device__ inline uint64_t lookback_wave(uint64_t *flags, uint64_t b, uint64_t s
     if (lane == 0)
         atomic_store_u64(&flags[b], FLAG_INC | (excl + size));
     return excl;
+}
+
+__device__ inline uint64_t lookback_wave(uint64_t *flags, uint64_t b, uint64_t size, uint32_t *status, uint32_t *fstatus)
+{
+    lookback_publish(flags, b, size);
+    return lookback_resolve(flags, b, size, status, fstatus);
 }
 
 }  // namespace czk
