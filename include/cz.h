@@ -105,8 +105,10 @@ void cz_destroy(cz_ctx *ctx);
 /* Grow the context's workspace so that fields of up to max_blocks blocks need
  * no allocation later: the look-back flags (8 bytes a block) and the slots in
  * which single-field compression of 32^3 blocks parks records of at most
- * 8 KiB until their offsets are known (8 KiB + 4 bytes a block).  Optional:
- * compress/decompress grow the workspace on demand. */
+ * 8 KiB until their offsets are known (8 KiB + 4 bytes a block).  64^3 blocks
+ * also need scratch slots sized by the launch, not by the field (up to about
+ * 1 GiB for double data), which the first call with N = 64 allocates.
+ * Optional: compress/decompress grow the workspace on demand. */
 int cz_reserve(cz_ctx *ctx, uint64_t max_blocks);
 
 /* Worst-case stream size (every coefficient kept) for params p, or 0 when p
