@@ -955,11 +955,17 @@ __global__ __launch_bounds__(64 * INV8_WAVES) void inv_small8_kernel(Queue q)
     constexpr uint32_t MASK_BYTES = 64;
     using CU64 = const __attribute__((address_space(4))) uint64_t;
     using CU32 = const __attribute__((address_space(4))) uint32_t;
-    __shared__ T lds[INV8_WAVES * N * PS];
+    // float: the group's blocks are stored together, row by row (an 8^3
+    // float block's rows are 32 bytes, and written one block at a time they
+    // ran at a third of the double blocks' rate); double rows are 64 bytes and
+    // the LDS of four regions a wavefront would halve the resident groups
+    constexpr bool ROWS = sizeof(T) == 4;
+    constexpr int REGIONS = ROWS ? IK : 1;
+    __shared__ T lds[INV8_WAVES * REGIONS * N * PS];
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / 64;
     const int x = lane % N, y = lane / N;
-    T *reg = lds + wave * N * PS;
+    T *reg = lds + wave * REGIONS * N * PS;
     const uint64_t nw = (uint64_t)gridDim.x * INV8_WAVES;
     for (uint64_t g = (uint64_t)blockIdx.x * INV8_WAVES + wave; g * IK < q.ntickets; g += nw) {
         bool ok[IK];
@@ -1027,33 +1033,98 @@ __global__ __launch_bounds__(64 * INV8_WAVES) void inv_small8_kernel(Queue q)
                 pre += (uint32_t)__popcll(w[z]);
             }
         }
-        // transforms and stores, one block after another
+        if constexpr (!ROWS) {
+            // transforms and stores, one block after another
 #pragma unroll
-        for (int j = 0; j < IK; ++j) {
-            if (!ok[j])
-                continue;
-            line_inv<T, S, N>(c[j]);
+            for (int j = 0; j < IK; ++j) {
+                if (!ok[j])
+                    continue;
+                line_inv<T, S, N>(c[j]);
 #pragma unroll
-            for (int z = 0; z < N; ++z)
-                reg[z * PS + y * PX + x] = c[j][z];
-            wave_lds_sync();
-            slab_lines<T, S, N, 1, PX, PS, true>(reg, lane);  // y-lines
-            wave_lds_sync();
-            slab_lines<T, S, N, 0, PX, PS, true>(reg, lane);  // x-lines
-            wave_lds_sync();
-            const FieldView a = field_view(q, fld[j]);
-            const uint64_t b = ob[j];
-            const size_t plane = (size_t)a.nx * a.ny;
-            const uint32_t bx = (uint32_t)(b % a.nbx);
-            const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
-            const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
-            T *blk = static_cast<T *>(a.dst) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
-            const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
-            const uint32_t lane_off = ((uint32_t)y * a.nx + (uint32_t)x) * (uint32_t)sizeof(T);
+                for (int z = 0; z < N; ++z)
+                    reg[z * PS + y * PX + x] = c[j][z];
+                wave_lds_sync();
+                slab_lines<T, S, N, 1, PX, PS, true>(reg, lane);  // y-lines
+                wave_lds_sync();
+                slab_lines<T, S, N, 0, PX, PS, true>(reg, lane);  // x-lines
+                wave_lds_sync();
+                const FieldView a = field_view(q, fld[j]);
+                const uint64_t b = ob[j];
+                const size_t plane = (size_t)a.nx * a.ny;
+                const uint32_t bx = (uint32_t)(b % a.nbx);
+                const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
+                const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
+                T *blk = static_cast<T *>(a.dst) + ((size_t)bz * N * plane + (size_t)by * N * a.nx + (size_t)bx * N);
+                const uint32_t slab_bytes = ((uint32_t)(N - 1) * a.nx + N) * (uint32_t)sizeof(T);
+                const uint32_t lane_off = ((uint32_t)y * a.nx + (uint32_t)x) * (uint32_t)sizeof(T);
 #pragma unroll
-            for (int z = 0; z < N; ++z)
-                buf_store(reg[z * PS + y * PX + x], make_rsrc(blk + (size_t)z * plane, slab_bytes), lane_off);
-            wave_lds_sync();  // the region is rewritten by the next block
+                for (int z = 0; z < N; ++z)
+                    buf_store(reg[z * PS + y * PX + x], make_rsrc(blk + (size_t)z * plane, slab_bytes), lane_off);
+                wave_lds_sync();  // the region is rewritten by the next block
+            }
+        } else {
+            // transforms, one block after another, each in its own LDS region
+#pragma unroll
+            for (int j = 0; j < IK; ++j) {
+                if (!ok[j])
+                    continue;
+                T *rj = reg + j * N * PS;
+                line_inv<T, S, N>(c[j]);
+#pragma unroll
+                for (int z = 0; z < N; ++z)
+                    rj[z * PS + y * PX + x] = c[j][z];
+                wave_lds_sync();
+                slab_lines<T, S, N, 1, PX, PS, true>(rj, lane);  // y-lines
+                wave_lds_sync();
+                slab_lines<T, S, N, 0, PX, PS, true>(rj, lane);  // x-lines
+            }
+            wave_lds_sync();
+            // stores of the whole group: its blocks are consecutive, usually
+            // x-neighbours in one row of blocks, so a plane's rows of all IK
+            // blocks go out together (lane l of a store takes element x' = l mod
+            // IK N of row y of the group's plane, block x' / N), whole cache lines
+            // instead of one N-element segment per block and row
+            T *base[IK];
+            size_t pl[IK];
+            uint32_t rowp[IK];
+#pragma unroll
+            for (int j = 0; j < IK; ++j) {
+                const FieldView a = field_view(q, fld[j]);
+                const uint64_t b = ob[j];
+                pl[j] = (size_t)a.nx * a.ny;
+                rowp[j] = a.nx;
+                const uint32_t bx = (uint32_t)(b % a.nbx);
+                const uint32_t by = (uint32_t)((b / a.nbx) % a.nby);
+                const uint32_t bz = (uint32_t)(b / ((uint64_t)a.nbx * a.nby));
+                base[j] = static_cast<T *>(a.dst) + ((size_t)bz * N * pl[j] + (size_t)by * N * a.nx + (size_t)bx * N);
+            }
+            constexpr int W = IK * N;                  // elements of a group row
+            constexpr int STORES = IK * N * N / 64;    // store instructions per plane
+            static_assert((IK * N * N) % 64 == 0 && 64 % W == 0, "whole group rows per store");
+#pragma unroll
+            for (int z = 0; z < N; ++z) {
+#pragma unroll
+                for (int k = 0; k < STORES; ++k) {
+                    const int e = k * 64 + lane;
+                    const int yy = e / W, xx = e % W, j = xx / N, xj = xx % N;
+                    bool okj = false;
+                    T *bj = nullptr;
+                    size_t plj = 0;
+                    uint32_t rpj = 0;
+#pragma unroll
+                    for (int i = 0; i < IK; ++i) {
+                        if (j == i) {
+                            okj = ok[i];
+                            bj = base[i];
+                            plj = pl[i];
+                            rpj = rowp[i];
+                        }
+                    }
+                    if (okj)
+                        bj[(size_t)z * plj + (size_t)yy * rpj + xj] = reg[j * N * PS + z * PS + yy * PX + xj];
+                }
+            }
+            wave_lds_sync();  // the regions are rewritten by the next group
         }
     }
 }
