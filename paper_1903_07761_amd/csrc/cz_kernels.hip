@@ -1294,8 +1294,9 @@ __global__ __launch_bounds__(N *N / R, (InvWaves<T, N, Z, R>::value)) void inv_k
 }
 
 // ------------------------------------------------- scratch-staged blocks
-// Blocks too large for a CU (N = 64: 1 MiB float, 2 MiB double) live in a
-// per-workgroup scratch slot in global memory between passes.  Each level's
+// Blocks too large for a CU (N = 64: 1 MiB float, 2 MiB double) live in
+// per-workgroup scratch slots in global memory between passes (one a
+// workgroup in the inverse, two in the forward).  Each level's
 // x- and y-lines run on chunks of z-planes staged through LDS (row pitch
 // n + 1), the finest level reading its rows straight from the field (forward)
 // or writing them straight to it (inverse); the z-lines run in registers,
@@ -2326,7 +2327,7 @@ static int occupancy_small_t()
 int occupancy(const KernelKey &key, bool inverse)
 {
     if (key.block == 64)
-        return 1;  // one scratch slot per workgroup, one workgroup per CU
+        return 1;  // one workgroup per CU, its blocks staged in its scratch slots
     if (!inverse && key.block <= 16) {
         const bool f = key.elem_bytes == 4;
         if (key.block == 8)
