@@ -113,12 +113,24 @@ def test_tuner_keeps_the_default_within_the_margin():
     assert pick([0.5, 0.4, 0.45]) == 1
 
 
+def test_tuner_ignores_the_forward_where_it_has_one_tiling():
+    """8^3 and 16^3 blocks: the forward kernel takes no variant, so only the
+    inverse times decide; other sizes compare forward + inverse."""
+    from paper_1903_07761_amd.autotune import MARGIN, pick_entry
+
+    fwd = [0.50, 0.55]  # noise in a kernel that does not change
+    inv = [0.40, 0.40 * (1 - 2 * MARGIN)]
+    assert pick_entry(16, fwd, inv) == 1
+    assert pick_entry(8, [0.5], [0.4]) == 0
+    assert pick_entry(32, fwd + [0.9], inv + [0.4]) == 0  # the totals: 0.90, 0.926, 1.3
+
+
 def test_committed_table_follows_its_own_times(czlib):
     """Every entry of the committed table names a variant that exists and is
     the one the tuner's rule picks from the times recorded beside it."""
     import json
 
-    from paper_1903_07761_amd.autotune import DEFAULT_TABLE, pick
+    from paper_1903_07761_amd.autotune import DEFAULT_TABLE, pick_entry
 
     with open(DEFAULT_TABLE) as fh:
         table = json.load(fh)
@@ -128,4 +140,4 @@ def test_committed_table_follows_its_own_times(czlib):
             nkey, tkey, _ = k.split("/")
             nv = czlib.variant_count(int(nkey[1:]), 4 if tkey == "f32" else 8)
             assert len(v["fwd_ms"]) == len(v["inv_ms"]) == nv, k
-            assert v["variant"] == pick([a + b for a, b in zip(v["fwd_ms"], v["inv_ms"])]), (arch, k)
+            assert v["variant"] == pick_entry(int(nkey[1:]), v["fwd_ms"], v["inv_ms"]), (arch, k)
